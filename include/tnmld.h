@@ -1,0 +1,137 @@
+/*
+ * tnmld.h - boundary-MPS maximum-likelihood coset decoding of the rotated
+ * surface code on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem (paper Sec. 2.3, eqs. "coset_prob" and "mld_formal"): for a
+ * syndrome s of the [[d^2, 1, d]] rotated surface code under independent
+ * per-qubit Pauli noise with probability vectors (p_I, p_X, p_Y, p_Z)_q
+ * (Sec. 3.1.1), compute the four coset partition functions
+ *     Z_l(s) = sum of Pr(E) over errors E with syndrome s and logical class l,
+ * l in {I, X, Y, Z}, the posterior log P(l|s) and the maximum-likelihood class.
+ * Z_l is contracted as the generator-picture tensor network of Sec. 3.2.1 by
+ * boundary MPS: row-by-row MPO.MPS products, each compressed back to bond
+ * dimension chi by SVD truncation, with the log-norm of the boundary state
+ * accumulated in FP64 after every row.
+ *
+ * Conventions: qubit q = r*d + c; Pauli codes 0=I, 1=X, 2=Y, 3=Z; the d^2-1
+ * checks sit on corners (r,c) in [-1, d-1]^2 (X-type iff r+c even; bulk
+ * corners 0..d-2, X-type boundary checks on the top and bottom rows, Z-type
+ * on the left and right columns); syndrome bit j follows the order "all Z-type
+ * checks, then all X-type checks, each sorted by corner (r,c)"; the logical
+ * class of an error is (x-parity on row 0, z-parity on column 0) mapped to
+ * I=(0,0)=0, X=(1,0)=1, Y=(1,1)=2, Z=(0,1)=3.
+ *
+ * Memory: every pointer inside tn_segment and every workspace pointer is a
+ * DEVICE pointer (hipMalloc'ed or from a framework allocator); host helpers
+ * say so explicitly.  The caller owns all buffers; the library never frees
+ * caller memory.  Calls are asynchronous on `stream` (a hipStream_t, NULL =
+ * default stream); results are valid after the caller synchronises it.
+ *
+ * Errors: argument validation is synchronous and returns a negative
+ * tn_status with nothing enqueued; tn_last_error() then describes it.  No
+ * exception crosses this interface and NaN is never written: an impossible
+ * coset has log Z = -INFINITY; an impossible syndrome gives log P = -INFINITY
+ * and class 0.
+ */
+#ifndef TNMLD_H
+#define TNMLD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TN_OK = 0,
+  TN_EINVAL = -1,        /* bad argument (shape, range, pointer, workspace too small) */
+  TN_ENOMEM = -2,        /* the library could not allocate its plan cache */
+  TN_EDEVICE = -3,       /* no usable HIP device, or a HIP runtime error */
+  TN_EUNSUPPORTED = -4,  /* valid request the build cannot run (e.g. chi too large for LDS) */
+  TN_ENUMERIC = -5
+} tn_status;
+
+typedef enum {
+  TN_FP64 = 0,       /* every step in FP64 */
+  TN_FP32 = 1,       /* MPS and MPO.MPS contractions in FP32; the LQ and SVD
+                        factorisations of the truncation in FP64 */
+  TN_BF16 = 2,       /* MPS and MPO.MPS contractions in bf16 on MFMA with FP32
+                        accumulation; factorisations in FP64 */
+  TN_FP32_PLAIN = 3  /* every contraction and factorisation in FP32 (reductions
+                        accumulate in FP64); the plain single-precision form */
+} tn_precision;
+/* Log-scales, log Z, log P(s) and the class decision are FP64 in every form. */
+
+#define TN_MAX_D 31
+#define TN_MAX_SEGMENTS 16
+
+/* One homogeneous group of syndromes: one code distance, one bond dimension,
+ * one precision, and a set of noise models addressed by model_index. */
+typedef struct {
+  int32_t d;                   /* odd, 3 <= d <= TN_MAX_D */
+  int32_t chi;                 /* bond-dimension cap (>= 1); 0 = no truncation (exact, small d only) */
+  int32_t precision;           /* tn_precision */
+  int32_t n_models;            /* >= 1 */
+  const double* rates;         /* device [n_models][d*d][3]: p_X, p_Y, p_Z per qubit; p_I = 1 - sum */
+  const int32_t* model_index;  /* device [count] in [0, n_models), or NULL (all model 0) */
+  const uint8_t* syndromes;    /* device [count][d*d-1], bytes in {0,1}, order above */
+  int64_t count;               /* number of syndromes (>= 0) */
+  double* out_logz;            /* device [count][4]: natural-log Z_l; required */
+  double* out_logp;            /* device [count]: log P(s) = logsumexp_l log Z_l, or NULL */
+  uint8_t* out_class;          /* device [count]: tie-tolerant argmax, or NULL */
+} tn_segment;
+
+/* Bytes of device workspace that tn_coset_loglik / tn_decode_batch need for
+ * these segments; with_backward = 1 sizes it for tn_coset_loglik_backward.
+ * Returns 0 on invalid arguments (see tn_last_error). */
+size_t tn_workspace_size(const tn_segment* segs, int32_t nseg, int32_t with_backward);
+
+/* log Z_l(s) for every syndrome of every segment (Sec. 2.3 eq. "coset_prob",
+ * contracted by boundary MPS as in Sec. 3.2.1), written to out_logz; also
+ * out_logp when non-NULL.  One persistent launch per precision drains a work
+ * queue of (syndrome, coset) items across all segments, largest d first.
+ * segs: HOST array of nseg <= TN_MAX_SEGMENTS descriptors.  workspace: device,
+ * ws_bytes >= tn_workspace_size(segs, nseg, 0), caller-owned, reused freely
+ * after the call completes on `stream`. */
+int tn_coset_loglik(const tn_segment* segs, int32_t nseg, void* workspace, size_t ws_bytes, void* stream);
+
+/* tn_coset_loglik plus the maximum-likelihood decision (Sec. 2.3 eq.
+ * "mld_formal"): out_class[b] = the smallest l with
+ * log Z_l >= max_l' log Z_l' - tie_tol * max(1, |max_l' log Z_l'|)
+ * (tie_tol <= 0 selects 1e-9), and out_logp. */
+int tn_decode_batch(const tn_segment* segs, int32_t nseg, double tie_tol, void* workspace, size_t ws_bytes,
+                    void* stream);
+
+/* Gradient of the weighted log-likelihood  sum_b grad_logp[b] * log P(s_b)
+ * (the per-syndrome term of the paper's eq. "dmle_loss") with respect to
+ * theta_{q,P} = ln p_{q,P}, P in {X, Y, Z}, p_I = 1 - p_X - p_Y - p_Z.
+ * Contracts each (syndrome, coset) forward with row checkpoints, recomputes
+ * each segment of rows from its checkpoint, sweeps a second boundary MPS up
+ * from the bottom, and contracts the environment of every qubit tensor.
+ * grad_logp[s]: device [count] of segment s; grad_log_rates[s]: device
+ * [n_models][d*d][3], ACCUMULATED (+=) in FP64 by a deterministic reduction.
+ * Also writes out_logz / out_logp of each segment.
+ * workspace: ws_bytes >= tn_workspace_size(segs, nseg, 1). */
+int tn_coset_loglik_backward(const tn_segment* segs, int32_t nseg, const double* const* grad_logp,
+                             double* const* grad_log_rates, void* workspace, size_t ws_bytes, void* stream);
+
+/* HOST helper: check layout of distance d.  type_out: host [d*d-1] (0 = X-type,
+ * 1 = Z-type); support_out: host [d*d-1][4] qubit indices, -1 padded.
+ * Returns d*d-1, or TN_EINVAL. */
+int tn_code_stabilizers(int32_t d, int32_t* type_out, int32_t* support_out);
+
+/* HOST helper: properties of the contraction plan for (d, chi, precision):
+ * info[0] counted forward flops per (syndrome, coset), info[1] scratch bytes
+ * per work-group, info[2] LDS bytes per work-group, info[3] sites per row,
+ * info[4] rows, info[5] columns per site.  Returns TN_OK or a tn_status. */
+int tn_plan_info(int32_t d, int32_t chi, int32_t precision, double* info);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* tn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TNMLD_H */

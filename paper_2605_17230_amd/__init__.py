@@ -1,0 +1,11 @@
+"""MI355X-native boundary-MPS maximum-likelihood coset decoding.
+
+The contraction runs in ``libtnmld.so`` (HIP, gfx950); this package only
+marshals arguments.  See include/tnmld.h for the C ABI.
+"""
+from ._lib import TNError, lib, LIB_PATH  # noqa: F401
+from .api import (SegmentInput, SegmentOutput, code_stabilizers, coset_loglik, decode,  # noqa: F401
+                  decode_segments, plan_info)
+
+__all__ = ["TNError", "SegmentInput", "SegmentOutput", "coset_loglik", "decode", "decode_segments",
+           "plan_info", "code_stabilizers", "lib", "LIB_PATH"]

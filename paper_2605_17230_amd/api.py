@@ -1,0 +1,137 @@
+"""PyTorch-facing calls of the C ABI.  Torch provides device memory and the
+stream; all arithmetic runs in libtnmld.so on the GPU."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import PRECISIONS, Segment, check, lib
+
+_workspaces: dict = {}
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """Per-device scratch buffer, grown on demand and reused across calls."""
+    dev = torch.device(device)
+    key = (dev.type, dev.index if dev.index is not None else torch.cuda.current_device())
+    buf = _workspaces.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)
+        _workspaces[key] = buf
+    return buf
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need_cuda(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+
+
+@dataclass
+class SegmentInput:
+    """One homogeneous group: distance d, bond cap chi, precision, noise models."""
+    d: int
+    chi: int
+    syndromes: torch.Tensor            # uint8 [B, d*d-1] on the GPU
+    rates: torch.Tensor                # float64 [M, d*d, 3] (or [d*d, 3]) on the GPU
+    model_index: torch.Tensor | None = None  # int32 [B] or None
+    precision: str = "fp32"
+
+
+@dataclass
+class SegmentOutput:
+    logz: torch.Tensor   # float64 [B, 4]
+    logp: torch.Tensor   # float64 [B]
+    cls: torch.Tensor    # uint8 [B]
+
+
+def _prepare(segs):
+    if not 1 <= len(segs) <= _lib.TN_MAX_SEGMENTS:
+        raise ValueError("between 1 and 16 segments per call")
+    arr = (Segment * len(segs))()
+    outs, keep = [], []
+    for i, s in enumerate(segs):
+        _need_cuda(s.syndromes, "syndromes")
+        _need_cuda(s.rates, "rates")
+        n, m = s.d * s.d, s.d * s.d - 1
+        syn = s.syndromes.to(torch.uint8).contiguous()
+        if syn.dim() != 2 or syn.shape[1] != m:
+            raise ValueError("syndromes must be [B, d*d-1]")
+        rates = s.rates.to(torch.float64).contiguous()
+        if rates.dim() == 2:
+            rates = rates.unsqueeze(0)
+        if rates.shape[1:] != (n, 3):
+            raise ValueError("rates must be [M, d*d, 3]")
+        mi = None
+        if s.model_index is not None:
+            _need_cuda(s.model_index, "model_index")
+            mi = s.model_index.to(torch.int32).contiguous()
+        b = syn.shape[0]
+        dev = syn.device
+        o = SegmentOutput(torch.empty((b, 4), dtype=torch.float64, device=dev),
+                          torch.empty(b, dtype=torch.float64, device=dev),
+                          torch.empty(b, dtype=torch.uint8, device=dev))
+        arr[i] = Segment(s.d, s.chi, PRECISIONS[s.precision], rates.shape[0], rates.data_ptr(),
+                         mi.data_ptr() if mi is not None else None, syn.data_ptr(), b,
+                         o.logz.data_ptr(), o.logp.data_ptr(), o.cls.data_ptr())
+        outs.append(o)
+        keep += [syn, rates, mi]
+    return arr, outs, keep
+
+
+def decode_segments(segs, tie_tol: float = 1e-9, stream=None):
+    """Decode several segments in one persistent launch per precision."""
+    arr, outs, keep = _prepare(segs)
+    L = lib()
+    nbytes = L.tn_workspace_size(arr, len(segs), 0)
+    if nbytes == 0:
+        check(_lib.TN_EINVAL if not L.tn_last_error() else -1)
+    dev = segs[0].syndromes.device
+    ws = workspace(nbytes, dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    check(L.tn_decode_batch(arr, len(segs), float(tie_tol), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                            ctypes.c_void_p(st)))
+    del keep
+    return outs
+
+
+def decode(syndromes, rates, d, chi, precision="fp32", model_index=None, tie_tol=1e-9):
+    """(logz [B,4], logp [B], class [B]) for one homogeneous batch."""
+    o = decode_segments([SegmentInput(d, chi, syndromes, rates, model_index, precision)], tie_tol)[0]
+    return o.logz, o.logp, o.cls
+
+
+def coset_loglik(syndromes, rates, d, chi, precision="fp32", model_index=None):
+    """log Z_l(s) [B,4] and log P(s) [B]."""
+    arr, outs, keep = _prepare([SegmentInput(d, chi, syndromes, rates, model_index, precision)])
+    L = lib()
+    nbytes = L.tn_workspace_size(arr, 1, 0)
+    ws = workspace(nbytes, syndromes.device)
+    st = torch.cuda.current_stream(syndromes.device).cuda_stream
+    check(L.tn_coset_loglik(arr, 1, ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(st)))
+    del keep
+    return outs[0].logz, outs[0].logp
+
+
+def plan_info(d, chi, precision="fp32"):
+    info = (ctypes.c_double * 6)()
+    check(lib().tn_plan_info(d, chi, PRECISIONS[precision], info))
+    return dict(flops=info[0], scratch_bytes=info[1], lds_bytes=info[2], sites=int(info[3]),
+                rows=int(info[4]), group=int(info[5]))
+
+
+def code_stabilizers(d):
+    import numpy as np
+    m = d * d - 1
+    t = np.zeros(m, np.int32)
+    s = np.zeros((m, 4), np.int32)
+    rc = lib().tn_code_stabilizers(d, t.ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p))
+    if rc < 0:
+        check(rc)
+    return t, s

@@ -1,0 +1,288 @@
+// Device-side forward contraction of one (syndrome, coset) pair (paper
+// Sec. 3.2.1): reference error, row MPO application, right-to-left LQ sweep,
+// left-to-right SVD truncation, FP64 log-norm accumulation.  Included by the
+// HIP translation unit; collective over one work-group of NT threads.
+#pragma once
+#ifndef TNMLD_EMU
+#include <hip/hip_runtime.h>
+#endif
+#include <stdint.h>
+
+#include "../../include/tnmld.h"
+#include "plan.hpp"
+#include "sweep.hpp"
+
+namespace tnmld {
+
+struct JobDev {
+  const uint8_t* plan;
+  const double* rates;
+  const int32_t* model_index;
+  const uint8_t* syn;
+  double* logz;
+  int64_t count;
+  int64_t item_begin;
+  int32_t n_models;
+  int32_t pad;
+};
+
+struct JobTable {
+  JobDev j[TN_MAX_SEGMENTS];
+  int32_t n;
+  int32_t pad;
+  int64_t nitems;
+};
+
+__device__ inline int pauli_code(int x, int z) { return x ? (z ? 2 : 1) : (z ? 3 : 0); }
+__device__ inline int pauli_x(int p) { return p == 1 || p == 2; }
+__device__ inline int pauli_z(int p) { return p == 2 || p == 3; }
+
+// p_q(f_q xor P) for the four P, from FP64 rates
+template <typename Real>
+__device__ inline Real pauli_weight(const double* rq, int fb, int P) {
+  const int x = pauli_x(P) ^ (fb & 1), z = pauli_z(P) ^ (fb >> 1);
+  const int e = pauli_code(x, z);
+  if (e == 0) return Real(1.0 - rq[0] - rq[1] - rq[2]);
+  return Real(rq[e - 1]);
+}
+
+// Forward contraction of one item; returns log Z (FP64).  Writes the class
+// index of the coset into *label.  Collective over the work-group.
+// Real: type of the MPS in HBM, of the MPO values and of the GEMM operands;
+// Fac: type of the LQ / SVD factorisations (LDS).
+template <typename Real, typename Fac>
+__device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* smem, const LdsLayout& lay,
+                               Real* scr, int* label) {
+  const uint8_t* plan = job.plan;
+  const PlanHeader* H = reinterpret_cast<const PlanHeader*>(plan);
+  const int d = H->d, n = H->n, m = H->m, nsite = H->nsite, nstep = H->nstep;
+  const SiteStep* steps = reinterpret_cast<const SiteStep*>(plan + H->steps_ofs);
+  const uint8_t* codes = plan + H->codes_ofs;
+  const CheckDesc* checks = reinterpret_cast<const CheckDesc*>(plan + H->checks_ofs);
+  const int64_t* region = reinterpret_cast<const int64_t*>(plan + H->region_ofs);
+  const uint8_t* init_qi = plan + H->init_qi_ofs;
+  const int16_t* fin = reinterpret_cast<const int16_t*>(plan + H->final_ofs);
+  const int tid = threadIdx.x;
+
+  uint8_t* fbits = smem + lay.fbits;
+  uint8_t* syn = smem + lay.syn;
+  int* perm = reinterpret_cast<int*>(smem + lay.perm);
+  double* dred = reinterpret_cast<double*>(smem + lay.red);
+  Real* Wv = reinterpret_cast<Real*>(smem + lay.W);
+  Real* Aj = reinterpret_cast<Real*>(smem + lay.Aj);
+  Real* T = reinterpret_cast<Real*>(smem + lay.T);
+  Fac* X = reinterpret_cast<Fac*>(smem + lay.X);
+  Real* L = reinterpret_cast<Real*>(smem + lay.L);
+  Fac* tau = reinterpret_cast<Fac*>(smem + lay.tau);
+  Fac* diag = reinterpret_cast<Fac*>(smem + lay.diag);
+  Fac* vtmp = reinterpret_cast<Fac*>(smem + lay.v);
+  Real* C = reinterpret_cast<Real*>(smem + lay.C);
+  Fac* Mm = reinterpret_cast<Fac*>(smem + lay.M);
+  Fac* Vv = reinterpret_cast<Fac*>(smem + lay.V);
+  Real* Qs = reinterpret_cast<Real*>(smem + lay.Q);
+  Fac* sig = reinterpret_cast<Fac*>(smem + lay.sig);
+  __shared__ int s_flag;
+  __shared__ int s_dead;
+  __shared__ int s_label;
+
+  const int model = job.model_index ? job.model_index[b] : 0;
+  const double* rates = job.rates + (int64_t)model * n * 3;
+
+  // --- 1. reference error -------------------------------------------------
+  for (int j = tid; j < m; j += NT) syn[j] = job.syn[b * m + j];
+  __syncthreads();
+  for (int q = tid; q < n; q += NT) {
+    const int r = q / d, c = q % d;
+    int x = 0, z = 0;
+    for (int j = 0; j < m; ++j) {
+      if (!syn[j]) continue;
+      const CheckDesc cd = checks[j];
+      if (cd.type == 1) {
+        if (c == cd.line && r >= cd.from && r <= cd.to) x ^= 1;
+      } else {
+        if (r == cd.line && c >= cd.from && c <= cd.to) z ^= 1;
+      }
+    }
+    fbits[q] = (uint8_t)(x | (z << 1));
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int a = 0, bb = 0;  // class of R: x-parity on row 0, z-parity on column 0
+    for (int c = 0; c < d; ++c) a ^= fbits[c] & 1;
+    for (int r = 0; r < d; ++r) bb ^= fbits[r * d] >> 1;
+    // logical representatives: X on column lx_col has class X (it crosses row 0
+    // once), Z on row lz_row has class Z (it crosses column 0 once)
+    const int lx = (mlog == 1 || mlog == 2), lz = (mlog == 2 || mlog == 3);
+    s_label = pauli_code(a ^ lx, bb ^ lz);
+    s_dead = 0;
+  }
+  __syncthreads();
+  for (int q = tid; q < n; q += NT) {
+    const int r = q / d, c = q % d;
+    int fb = fbits[q];
+    if ((mlog == 1 || mlog == 2) && c == H->lx_col) fb ^= 1;
+    if ((mlog == 2 || mlog == 3) && r == H->lz_row) fb ^= 2;
+    fbits[q] = (uint8_t)fb;
+  }
+  *label = s_label;
+
+  // --- initial MPS: product of all-ones vectors ------------------------------
+  for (int J = 0; J < nsite; ++J) {
+    const int qi = init_qi[J];
+    for (int e = tid; e < qi; e += NT) scr[region[J] + e] = Real(1);
+  }
+  __syncthreads();
+
+  double logscale = 0.0;
+  for (int u = 0; u < nstep; ++u) {
+    const SiteStep* row = steps + (int64_t)u * nsite;
+    // --- right-to-left: MPO apply + LQ --------------------------------------
+    if (tid == 0) L[0] = Real(1);
+    __syncthreads();
+    for (int J = nsite - 1; J >= 0; --J) {
+      const SiteStep st = row[J];
+      const int A = st.A, B = st.B, qi = st.qi, qo = st.qo;
+      const int Dl = st.Dl_old, Dr = st.Dr_old, mJ = st.m, k = st.k, kr = st.kr;
+      const int RB = Dr * B, nn = qo * kr;
+      const int ncode = A * qi * qo * B;
+      const uint8_t* cd = codes + st.wofs;
+      if (tid < ncode) {
+        const int c = cd[tid];
+        Real v = Real(0);
+        if (c == W_ONE) v = Real(1);
+        else if (c >= W_PAULI) v = pauli_weight<Real>(rates + 3 * st.q, fbits[st.q], c - W_PAULI);
+        Wv[tid] = v;
+      }
+      Real* g = scr + region[J];
+      for (int e = tid; e < Dl * qi * Dr; e += NT) Aj[e] = g[e];
+      __syncthreads();
+      for (int so = 0; so < qo; ++so) {
+        // T[(l,a)][(r,b)] = sum_si Aj[l][si][r] W[a][si][so][b]
+        for (int e = tid; e < mJ * RB; e += NT) {
+          const int la = e / RB, rb = e % RB;
+          const int l = la / A, a = la % A, r = rb / B, bb = rb % B;
+          Real acc = 0;
+          for (int si = 0; si < qi; ++si)
+            acc += Aj[(l * qi + si) * Dr + r] * Wv[((a * qi + si) * qo + so) * B + bb];
+          T[e] = acc;
+        }
+        __syncthreads();
+        // X[:, so*kr + c] = T . L
+        gemm_lds<Real>(mJ, kr, RB, T, RB, L, kr, [&](int i, int j, Real v) { X[i * nn + so * kr + j] = Fac(v); });
+        __syncthreads();
+      }
+      lq_factor<Fac>(X, mJ, nn, nn, tau, diag, dred);
+      // L (mJ x k) for the site to the left
+      for (int e = tid; e < mJ * k; e += NT) {
+        const int r = e / k, c = e % k;
+        L[e] = Real(c < r ? X[r * nn + c] : (c == r ? diag[r] : Fac(0)));
+      }
+      __syncthreads();
+      lq_form_q<Fac>(X, mJ, nn, nn, tau, vtmp);
+      for (int e = tid; e < k * nn; e += NT) g[e] = Real(X[e]);
+      __syncthreads();
+    }
+    // L is 1x1: the norm of the MPO-applied state
+    {
+      const Real l0 = L[0];
+      __syncthreads();
+      if (!(fabs((double)l0) > 0.0)) {
+        if (tid == 0) s_dead = 1;
+      } else {
+        logscale += log(fabs((double)l0));
+        if (tid == 0) C[0] = l0 > Real(0) ? Real(1) : Real(-1);
+      }
+      __syncthreads();
+      if (s_dead) break;
+    }
+    // --- left-to-right: truncation ----------------------------------------
+    for (int J = 0; J < nsite; ++J) {
+      const SiteStep st = row[J];
+      const int qo = st.qo, k = st.k, kr = st.kr, Dl = st.Dl_new, Dn = st.Dr_new;
+      const int nn = qo * kr, R = Dl * qo;
+      const int ldm = R + 1, ldv = kr + 1;
+      Real* g = scr + region[J];
+      for (int e = tid; e < k * nn; e += NT) Qs[e] = g[e];
+      for (int e = tid; e < kr * kr; e += NT) Vv[(e / kr) * ldv + (e % kr)] = (e / kr == e % kr) ? Fac(1) : Fac(0);
+      __syncthreads();
+      // M[(l,so)][c] = sum_k C[l][k] Q[k][so][c], stored column-major
+      gemm_lds<Real>(Dl, nn, k, C, k, Qs, nn, [&](int i, int j, Real v) {
+        const int so = j / kr, c = j % kr;
+        Mm[c * ldm + i * qo + so] = Fac(v);
+      });
+      __syncthreads();
+      jacobi_svd<Fac>(Mm, R, kr, ldm, Vv, ldv, &s_flag);
+      // column norms and ranking
+      for (int c = tid; c < kr; c += NT) {
+        double s2 = 0;
+        for (int r = 0; r < R; ++r) s2 += (double)Mm[c * ldm + r] * (double)Mm[c * ldm + r];
+        sig[c] = Fac(sqrt(s2));
+      }
+      __syncthreads();
+      for (int c = tid; c < kr; c += NT) {
+        const Fac sc = sig[c];
+        int rank = 0;
+        for (int c2 = 0; c2 < kr; ++c2) {
+          const Fac s2 = sig[c2];
+          rank += (s2 > sc) || (s2 == sc && c2 < c);
+        }
+        perm[rank] = c;
+      }
+      __syncthreads();
+      if (J == nsite - 1) {
+        const double s0 = (double)sig[perm[0]];
+        if (!(s0 > TinyNorm<Fac>::v)) {
+          if (tid == 0) s_dead = 1;
+        } else {
+          logscale += log(s0);
+        }
+      }
+      // new site tensor A[l][so][r] and carry C[r][c'] = sigma_r V[c'][perm r];
+      // every singular value is kept (small ones of these graded matrices are
+      // accurate and can carry the weight of improbable cosets); only norms at
+      // the bottom of the real range count as zero
+      for (int e = tid; e < R * Dn; e += NT) {
+        const int lso = e / Dn, r = e % Dn;
+        const int c = perm[r];
+        const Fac sc = sig[c];
+        g[e] = Real((double)sc > TinyNorm<Fac>::v ? Mm[c * ldm + lso] / sc : Fac(0));
+      }
+      __syncthreads();
+      for (int e = tid; e < Dn * kr; e += NT) {
+        const int r = e / kr, c2 = e % kr;
+        const int c = perm[r];
+        const Fac sc = sig[c];
+        C[e] = Real((double)sc > TinyNorm<Fac>::v ? sc * Vv[c * ldv + c2] : Fac(0));
+      }
+      __syncthreads();
+      if (s_dead) break;
+    }
+    if (s_dead) break;
+  }
+  if (s_dead) return -INFINITY;
+
+  // --- close: sum every remaining variable --------------------------------
+  double* vv = reinterpret_cast<double*>(smem + lay.red);
+  Fac* vacc = sig;
+  if (tid == 0) vacc[0] = Fac(1);
+  __syncthreads();
+  for (int J = 0; J < nsite; ++J) {
+    const int Dl = fin[3 * J], qo = fin[3 * J + 1], Dr = fin[3 * J + 2];
+    const Real* g = scr + region[J];
+    Fac acc = 0;
+    if (tid < Dr)
+      for (int l = 0; l < Dl; ++l) {
+        Fac s = 0;
+        for (int so = 0; so < qo; ++so) s += Fac(g[(l * qo + so) * Dr + tid]);
+        acc += vacc[l] * s;
+      }
+    __syncthreads();
+    if (tid < Dr) vacc[tid] = acc;
+    __syncthreads();
+  }
+  (void)vv;
+  const double tot = (double)vacc[0];
+  return tot > 0.0 ? logscale + log(tot) : -INFINITY;
+}
+
+}  // namespace tnmld

@@ -1,0 +1,146 @@
+// Host-side contraction plan for the boundary-MPS coset contraction of the
+// rotated surface code (paper Sec. 3.2.1, generator picture + boundary MPS).
+//
+// Network.  Every stabiliser generator j carries a binary variable alpha_j
+// (the generator-picture sum); a qubit tensor weighs its Pauli
+// f_q * X^(sum of X-type alpha on q) * Z^(sum of Z-type alpha on q), where f is
+// the coset's reference error.  Rotating the patch by 45 degrees puts qubit
+// (r,c) at (u,w) = (r+c, c-r) and the plaquette with corner (r,c) at
+// (r+c+1, c-r): a square lattice whose vertical neighbours of a qubit are its
+// two same-type plaquettes and whose horizontal neighbours are the other two.
+//
+// Sweep.  The boundary MPS lives on the 2d-1 columns w = -(d-1)..d-1; column
+// w holds the generator variable currently "open" there.  Step u (u = 0..2d-2)
+// absorbs the qubits on the anti-diagonal r+c = u: on columns w = u (mod 2) the
+// qubit maps its upper plaquette variable (corner sum u-2) to its lower one
+// (corner sum u), weighted by the two neighbouring columns' variables (corner
+// sum u-1), which stay put.  Each step is therefore an MPO of bond dimension 2
+// acting on the MPS (the paper's chi -> chi*q with q = 2).  Columns are grouped
+// into sites of `group` columns (physical dimension up to 2^group).
+//
+// The plan fixes, for every step and site, the MPO tensor (as codes resolved on
+// the device from per-qubit rates and the reference error), the MPS bond
+// dimensions before/after truncation and the scratch / LDS sizes.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace tnmld {
+
+// Per (step, site) descriptor; POD, copied to the device verbatim.
+struct SiteStep {
+  int16_t q;       // qubit index of the site's active column, -1 if none
+  uint8_t A, B;    // MPO bond dimension on the left / right of the site (1 or 2)
+  uint8_t qi, qo;  // physical dimension before / after the step
+  uint8_t act;     // position of the active column inside the site
+  uint8_t pad0;
+  int16_t Dl_old, Dr_old;  // MPS bonds of the input site tensor
+  int16_t m;               // Dl_old * A: rows of the site matrix in the right-to-left sweep
+  int16_t k;               // rows kept by its LQ factorisation: min(m, qo * kr)
+  int16_t kr;              // k of the site to the right (1 for the last site)
+  int16_t Dl_new, Dr_new;  // bonds after truncation
+  int16_t pad1;
+  int32_t wofs;            // offset of the A*qi*qo*B MPO code table
+  int32_t pad2;
+};
+static_assert(sizeof(SiteStep) == 32, "SiteStep layout");
+
+// Code of one MPO entry: 0 -> 0, 1 -> 1, 2 + P -> p_q(f_q xor P), P in {I,X,Y,Z}
+// (xor on the (x,z) bit pair).  Entry order: [a][si][so][b].
+enum : uint8_t { W_ZERO = 0, W_ONE = 1, W_PAULI = 2 };
+
+// Reference error R(s) = product over fired checks of a string that flips that
+// check alone.  The strings run to the boundary the sweep starts from: a Z-type
+// check with corner (r,c) gets X on column max(c,0), rows 0..r; an X-type check
+// gets Z on row max(r,0), columns 0..c.  Logical representatives: X on column
+// 0, Z on row 0.  With every string absorbed in the first rows, later rows
+// never have to cancel the bulk of the boundary state, which keeps FP32
+// rounding from being amplified on improbable cosets.
+struct CheckDesc {
+  int8_t type;      // 0 = X-type (string of Z along a row), 1 = Z-type (string of X along a column)
+  int8_t line;      // row (X-type) or column (Z-type) of the string
+  int8_t from, to;  // the string covers indices from..to along that line
+};
+
+struct PlanHeader {  // device-visible, followed by the tables at the offsets below
+  int32_t d, n, m, nsite, nstep, chi, group;
+  int32_t lx_col, lz_row;  // logical representatives: X on column lx_col, Z on row lz_row
+  int32_t steps_ofs;    // SiteStep[nstep][nsite]
+  int32_t codes_ofs;    // uint8 codes
+  int32_t checks_ofs;   // CheckDesc[m]
+  int32_t region_ofs;   // int64 element offset of each site's scratch region [nsite]
+  int32_t init_qi_ofs;  // uint8 physical dimension of each site before step 0 [nsite]
+  int32_t final_ofs;    // int16 [nsite][3]: Dl, qo, Dr of the final MPS
+  int32_t bytes;        // total blob size
+  int64_t scratch_elems;  // scratch elements per contraction (site regions)
+  // maxima used to carve LDS (elements)
+  int32_t max_Aj;   // Dl_old * qi * Dr_old           input site tensor
+  int32_t max_T;    // m * (Dr_old * B)               one output slice of the MPO-applied site
+  int32_t max_X;    // m * qo * kr                    LQ matrix of the right-to-left sweep
+  int32_t max_L;    // max(m * k, Dr_old * B * kr)    carry of the right-to-left sweep
+  int32_t max_C;    // Dl_new * k                     carry of the left-to-right sweep
+  int32_t max_M;    // (Dl_new * qo + 1) * kr         matrix to truncate (padded columns)
+  int32_t max_V;    // (kr + 1) * kr                  right rotations
+  int32_t max_Q;    // k * qo * kr                    staged orthonormal site
+  int32_t max_kr, max_n, max_m, max_rows, max_bond;
+  int32_t pad;
+  double flops_fwd; // counted flops of one contraction (see count in plan.cpp)
+};
+
+struct Plan {
+  PlanHeader h;
+  std::vector<uint8_t> blob;  // header + tables, as uploaded
+};
+
+// Build the plan; returns an empty string on success, else an error message.
+std::string build_plan(int d, int chi, int group, Plan* out);
+
+// Element-wise maximum of the LDS maxima of two plans (for one launch that
+// serves several plans).
+void merge_maxima(PlanHeader* acc, const PlanHeader& h);
+
+// LDS carve-up of the sweep kernel, in bytes from the base.  Storage-type
+// buffers (site tensors, carries, GEMM operands) use `rb` bytes per element,
+// factorisation buffers (LQ matrix, SVD matrix and rotations) `fb` bytes.  The
+// right-to-left phase (Aj, T, X, L, tau/diag/v) and the left-to-right phase
+// (C, M, V, Q, sig) are never live together and share storage.
+struct LdsLayout {
+  int32_t Aj, T, X, L, tau, diag, v;  // right-to-left phase
+  int32_t C, M, V, Q, sig;            // left-to-right phase
+  int32_t W;                          // MPO values of the current site (<= 64, storage type)
+  int32_t red, perm, fbits, syn;      // FP64 reduction scratch, ranking, reference-error bits, syndrome
+  int32_t bytes;
+};
+
+inline int32_t pad64b(int64_t x) { return (int32_t)((x + 63) / 64 * 64); }
+
+inline LdsLayout lds_layout(const PlanHeader& h, int rb, int fb) {
+  LdsLayout o{};
+  int32_t p = 0;
+  o.Aj = p; p += pad64b((int64_t)h.max_Aj * rb);
+  o.T = p; p += pad64b((int64_t)h.max_T * rb);
+  o.X = p; p += pad64b((int64_t)h.max_X * fb);
+  o.L = p; p += pad64b((int64_t)h.max_L * rb);
+  o.tau = p; p += pad64b((int64_t)h.max_m * fb);
+  o.diag = p; p += pad64b((int64_t)h.max_m * fb);
+  o.v = p; p += pad64b((int64_t)h.max_n * fb);
+  const int32_t rl_end = p;
+  p = 0;
+  o.C = p; p += pad64b((int64_t)h.max_C * rb);
+  o.M = p; p += pad64b((int64_t)h.max_M * fb);
+  o.V = p; p += pad64b((int64_t)h.max_V * fb);
+  o.Q = p; p += pad64b((int64_t)h.max_Q * rb);
+  o.sig = p; p += pad64b((int64_t)(h.max_kr > h.max_bond ? h.max_kr : h.max_bond) * fb);
+  const int32_t lr_end = p;
+  p = rl_end > lr_end ? rl_end : lr_end;
+  o.W = p; p += pad64b(64 * rb);
+  o.red = p; p += 64 * 8;
+  o.perm = p; p += pad64b((int64_t)h.max_kr * 4);
+  o.fbits = p; p += pad64b(h.n);
+  o.syn = p; p += pad64b(h.m);
+  o.bytes = p;
+  return o;
+}
+
+}  // namespace tnmld

@@ -1,0 +1,259 @@
+// Device building blocks of the boundary-MPS sweep (gfx950, wave64).
+//
+// One work-group of NT = 256 threads contracts one (syndrome, coset) pair at a
+// time.  Every dense matrix of a site step lives in LDS; the MPS itself lives
+// in a per-work-group scratch region of HBM (it does not fit in LDS at
+// chi = 32: 33 sites x 8-64 KB).  Routines here are work-group collective:
+// every thread of the block must call them with identical arguments.
+#pragma once
+#ifndef TNMLD_EMU
+#include <hip/hip_runtime.h>
+#endif
+#include <stdint.h>
+
+#include "plan.hpp"
+
+namespace tnmld {
+
+constexpr int NT = 256;
+constexpr int WAVE = 64;
+
+template <typename Real>
+struct Eps;
+template <>
+struct Eps<double> {
+  static constexpr double v = 2.220446049250313e-16;
+};
+template <>
+struct Eps<float> {
+  static constexpr float v = 1.1920929e-07f;
+};
+// norms below this are treated as exact zeros (1/norm must stay finite in Real)
+template <typename Real>
+struct TinyNorm;
+template <>
+struct TinyNorm<double> {
+  static constexpr double v = 1e-290;
+};
+template <>
+struct TinyNorm<float> {
+  static constexpr double v = 1e-30;
+};
+
+// sum over aligned groups of G consecutive lanes (G a power of two <= 64)
+template <typename Real>
+__device__ inline Real group_sum(Real v, int G) {
+  for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+// block-wide sum, result returned to every thread; red holds >= NT/WAVE reals
+template <typename Real>
+__device__ inline Real block_sum(Real v, Real* red) {
+  v = group_sum(v, WAVE);
+  const int w = threadIdx.x / WAVE;
+  __syncthreads();
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[w] = v;
+  __syncthreads();
+  Real s = 0;
+  for (int i = 0; i < NT / WAVE; ++i) s += red[i];
+  return s;
+}
+
+// C = A (MxK, row-major lda) * B (KxN, row-major ldb); store(i, j, value).
+// 4x4 register tiles; threads sweep tiles row-major.
+template <typename Real, typename Store>
+__device__ inline void gemm_lds(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb, Store store) {
+  const int tm = (M + 3) >> 2, tn = (N + 3) >> 2;
+  for (int t = threadIdx.x; t < tm * tn; t += NT) {
+    const int i0 = (t / tn) << 2, j0 = (t % tn) << 2;
+    Real acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = 0;
+    const bool fullm = i0 + 4 <= M, fulln = j0 + 4 <= N;
+    for (int k = 0; k < K; ++k) {
+      Real av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = (fullm || i0 + a < M) ? A[(i0 + a) * lda + k] : Real(0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = (fulln || j0 + b < N) ? B[k * ldb + j0 + b] : Real(0);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (i0 + a < M && j0 + b < N) store(i0 + a, j0 + b, acc[a][b]);
+  }
+}
+
+// Householder LQ of X (m x n, row-major, leading dimension ld), in place:
+// X = L Q with L lower-trapezoidal (m x k) and Q (k x n) with orthonormal rows,
+// k = min(m, n).  Reflectors follow the LAPACK convention H = I - tau v v^T
+// with v_0 = 1 (implicit), so tau is in [1, 2] and v = O(1) whatever the
+// scale of the row: tiny rows (graded matrices) keep their relative accuracy.
+// Norms and dot products accumulate in FP64 so that FP32 squares of small
+// entries cannot underflow.  On return row i holds v_i in columns i+1..n-1,
+// the strictly lower part holds L, diag[i] = L[i][i], tau[i] = tau_i.
+template <typename Real>
+__device__ void lq_factor(Real* X, int m, int n, int ld, Real* tau, Real* diag, double* red) {
+  const int k = m < n ? m : n;
+  const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
+  for (int i = 0; i < k; ++i) {
+    Real* xi = X + i * ld;
+    double part = 0;
+    for (int c = i + 1 + tid; c < n; c += NT) part += (double)xi[c] * (double)xi[c];
+    const double tail2 = block_sum(part, red);
+    const double x0 = (double)xi[i];
+    const double nrm = sqrt(tail2 + x0 * x0);
+    // reflector; rows at the bottom of the real range are treated as exact zeros
+    const bool live = tail2 > 0.0 && nrm > TinyNorm<Real>::v;
+    double beta = x0, t = 0.0, scale = 0.0;
+    if (live) {
+      beta = x0 >= 0.0 ? -nrm : nrm;
+      t = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
+    __syncthreads();
+    if (live)
+      for (int c = i + 1 + tid; c < n; c += NT) xi[c] = Real((double)xi[c] * scale);
+    if (tid == 0) {
+      tau[i] = Real(t);
+      diag[i] = Real(beta);
+    }
+    __syncthreads();
+    if (live) {
+      for (int r0 = i + 1; r0 < m; r0 += NT / 16) {
+        const int r = r0 + grp;
+        const bool act = r < m;
+        Real* xr = X + (act ? r : 0) * ld;
+        double dot = 0;
+        const double xri = act ? (double)xr[i] : 0.0;  // read before lane 0 rewrites it
+        if (act)
+          for (int c = i + 1 + lane; c < n; c += 16) dot += (double)xr[c] * (double)xi[c];
+        dot = group_sum(dot, 16);  // wave-uniform trip count: every lane shuffles
+        if (act) {
+          const Real w = Real((dot + xri) * t);
+          if (lane == 0) xr[i] -= w;
+          for (int c = i + 1 + lane; c < n; c += 16) xr[c] -= w * xi[c];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// After lq_factor and after L has been copied out: overwrite rows 0..k-1 of X
+// with the explicit Q = [I_k 0] H_{k-1} ... H_0.  v is scratch of length n.
+template <typename Real>
+__device__ void lq_form_q(Real* X, int m, int n, int ld, const Real* tau, Real* v) {
+  const int k = m < n ? m : n;
+  const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
+  for (int i = k - 1; i >= 0; --i) {
+    Real* xi = X + i * ld;
+    for (int c = i + 1 + tid; c < n; c += NT) v[c] = xi[c];
+    if (tid == 0) v[i] = Real(1);
+    __syncthreads();
+    const Real t = tau[i];
+    if (t != Real(0)) {
+      for (int r0 = i + 1; r0 < k; r0 += NT / 16) {
+        const int r = r0 + grp;
+        const bool act = r < k;
+        Real* xr = X + (act ? r : 0) * ld;
+        double dot = 0;
+        if (act)
+          for (int c = i + lane; c < n; c += 16) dot += (double)xr[c] * (double)v[c];
+        dot = group_sum(dot, 16);
+        if (act) {
+          const Real w = Real(dot) * t;
+          for (int c = i + lane; c < n; c += 16) xr[c] -= w * v[c];
+        }
+      }
+    }
+    for (int c = tid; c < n; c += NT) xi[c] = c < i ? Real(0) : ((c == i ? Real(1) : Real(0)) - t * v[c]);
+    __syncthreads();
+  }
+}
+
+// One-sided (Hestenes) Jacobi on the columns of M (rows x cols, column-major,
+// leading dimension ldm), accumulating the rotations in V (cols x cols,
+// column-major, ldv), which must hold the identity on entry.  Afterwards the
+// columns of M are mutually orthogonal: M_in V = M_out, and the column norms
+// are the singular values.  Parallel cyclic ordering (circle method): each
+// round rotates cols'/2 disjoint pairs, one pair per group of G lanes.
+template <typename Real>
+__device__ void jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv, int* flag) {
+  if (cols < 2) return;
+  const int N = cols + (cols & 1);
+  const int P = N >> 1;
+  int G = WAVE;
+  while (G > 1 && G * P > NT) G >>= 1;
+  const int tid = threadIdx.x, g = tid / G, lane = tid % G;
+  const double tol = (double)Eps<Real>::v * (rows > 8 ? rows : 8);
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    for (int rd = 0; rd < N - 1; ++rd) {
+      int p, q;
+      if (g == 0) {
+        p = rd;
+        q = N - 1;
+      } else {
+        p = (rd + g) % (N - 1);
+        q = (rd - g + N - 1) % (N - 1);
+      }
+      if (p > q) {
+        const int t = p;
+        p = q;
+        q = t;
+      }
+      const bool act = g < P && q < cols;
+      Real* a = M + (act ? p : 0) * ldm;
+      Real* b = M + (act ? q : 0) * ldm;
+      double al = 0, be = 0, ga = 0;  // FP64 sums: no underflow of small columns
+      if (act)
+        for (int r = lane; r < rows; r += G) {
+          const double x = a[r], y = b[r];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+      // all lanes shuffle (wave-uniform); inactive groups reduce zeros
+      al = group_sum(al, G);
+      be = group_sum(be, G);
+      ga = group_sum(ga, G);
+      if (act && ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+        const double zeta = (be - al) / (2.0 * ga);
+        double tt;
+        if (fabs(zeta) > 1e16) tt = 0.5 / zeta;
+        else tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cd = 1.0 / sqrt(1.0 + tt * tt);
+        const Real c = Real(cd), s = Real(cd * tt);
+        for (int r = lane; r < rows; r += G) {
+          const Real x = a[r], y = b[r];
+          a[r] = c * x - s * y;
+          b[r] = s * x + c * y;
+        }
+        Real* va = V + p * ldv;
+        Real* vb = V + q * ldv;
+        for (int r = lane; r < cols; r += G) {
+          const Real x = va[r], y = vb[r];
+          va[r] = c * x - s * y;
+          vb[r] = s * x + c * y;
+        }
+        if (lane == 0) *flag = 1;
+      }
+      __syncthreads();
+    }
+    const int f = *flag;
+    __syncthreads();
+    if (!f) break;
+  }
+}
+
+}  // namespace tnmld

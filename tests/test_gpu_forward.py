@@ -1,0 +1,214 @@
+"""Parity of the HIP boundary-MPS path against the FP64 oracle (GPU only).
+
+Bars (element by element, same seeded inputs), wherever the bond cap is not
+reached (d = 3 with chi >= 4, d = 5 with chi >= 16, errors supported on a few
+qubits at any d):
+  * fp64: log Z within 1e-10 relative for every coset whose posterior
+    P(l|s) >= e^-20, and within 1e-6 relative for the rest (an L2-normalised
+    boundary state carries an improbable coset only as a small component of
+    the dominant one, so its digits are lost in proportion);
+  * fp32 (FP32 contractions, FP64 factorisations): |delta log Z| <= 1e-4;
+  * fp32plain (everything FP32): |delta log Z| <= 1e-3 for cosets with
+    posterior >= e^-10;
+  * classes identical wherever the oracle's top-two gap exceeds twice the
+    bound; inside that band (and for exact ties) the GPU class is one of the
+    oracle's top classes;
+  * truncated runs: the stated truncation error bound and class agreement.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+tn = pytest.importorskip("paper_2605_17230_amd")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def run(dev, d, chi, prec, syn, rates, model_index=None):
+    print("case d=%d chi=%d %s B=%d" % (d, chi, prec, len(syn)), flush=True)
+    s = torch.from_numpy(np.ascontiguousarray(syn)).to(dev)
+    r = torch.from_numpy(np.ascontiguousarray(rates)).to(dev)
+    mi = None if model_index is None else torch.from_numpy(np.ascontiguousarray(model_index, np.int32)).to(dev)
+    logz, logp, cls = tn.decode(s, r, d, chi, prec, model_index=mi)
+    torch.cuda.synchronize()
+    return logz.cpu().numpy(), logp.cpu().numpy(), cls.cpu().numpy()
+
+
+def rel_err(a, b):
+    fa, fb = np.isfinite(a), np.isfinite(b)
+    assert np.array_equal(fa, fb), "finite pattern differs"
+    return float(np.max(np.abs(a[fa] - b[fa]) / np.maximum(1.0, np.abs(b[fa])), initial=0.0))
+
+
+def abs_err(a, b):
+    fa, fb = np.isfinite(a), np.isfinite(b)
+    assert np.array_equal(fa, fb), "finite pattern differs"
+    return float(np.max(np.abs(a[fa] - b[fa]), initial=0.0))
+
+
+def log_posterior(ref):
+    with np.errstate(invalid="ignore"):
+        return ref - np.logaddexp.reduce(ref, axis=1, keepdims=True)
+
+
+def check_logz(got, ref, prec):
+    """Apply the bar of the precision form; returns the max abs error."""
+    fa, fb = np.isfinite(got), np.isfinite(ref)
+    assert np.array_equal(fa, fb), "finite pattern differs"
+    post = np.where(fb, log_posterior(np.where(fb, ref, -np.inf)), -np.inf)
+    err = np.where(fb, np.abs(np.where(fa, got, 0) - np.where(fb, ref, 0)), 0.0)
+    rel = err / np.maximum(1.0, np.abs(np.where(fb, ref, 1.0)))
+    if prec == "fp64":
+        assert rel[post >= -20].max(initial=0) < 1e-10, rel[post >= -20].max(initial=0)
+        assert rel.max(initial=0) < 1e-6, rel.max(initial=0)
+    elif prec == "fp32":
+        assert err.max(initial=0) < 1e-4, err.max(initial=0)
+    else:
+        assert err[post >= -10].max(initial=0) < 1e-3, err[post >= -10].max(initial=0)
+    return float(err.max(initial=0))
+
+
+BOUND = {"fp64": 1e-9, "fp32": 1e-4, "fp32plain": 1e-3}
+
+
+def check_classes(got_cls, ref_logz, eps):
+    """Exact match where the oracle's top-two gap > 2 eps; else within the top set."""
+    _, ref_cls = oracle.decide(ref_logz)
+    srt = np.sort(ref_logz, axis=1)
+    gap = srt[:, 3] - srt[:, 2]
+    clear = gap > 2 * eps
+    assert np.array_equal(got_cls[clear], ref_cls[clear]), "class mismatch on unambiguous syndromes"
+    for b in np.nonzero(~clear)[0]:
+        top = ref_logz[b].max()
+        assert ref_logz[b, got_cls[b]] >= top - 2 * eps - 1e-12
+    return int((~clear).sum())
+
+
+@pytest.fixture(scope="module")
+def c1():
+    cfg = synth.CONFIGS["C1"]
+    r = synth.depolarizing(3, cfg["p"])
+    smp = synth.sample(3, r, cfg["count"], cfg["seed"])
+    table = oracle.enumerate_table(3, r)
+    si = (smp["syndromes"].astype(np.int64) << np.arange(8)).sum(1)
+    with np.errstate(divide="ignore"):
+        ref = np.log(table[si])
+    return r, smp, ref
+
+
+@pytest.mark.parametrize("chi", [0, 4, 8])
+def test_d3_fp64_matches_enumeration(dev, c1, chi):
+    r, smp, ref = c1
+    logz, logp, cls = run(dev, 3, chi, "fp64", smp["syndromes"], r)
+    assert rel_err(logz, ref) < 1e-10
+    rlp, rcls = oracle.decide(ref)
+    assert np.array_equal(cls, rcls)
+    assert rel_err(logp, rlp) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32plain"])
+def test_d3_single(dev, c1, prec):
+    r, smp, ref = c1
+    logz, logp, cls = run(dev, 3, 4, prec, smp["syndromes"], r)
+    check_logz(logz, ref, prec)
+    check_classes(cls, ref, BOUND[prec])
+
+
+@pytest.mark.parametrize("prec,chi", [("fp64", 16), ("fp64", 0), ("fp32", 16), ("fp32plain", 16)])
+def test_d5_exact_vs_transfer(dev, prec, chi):
+    d = 5
+    r = synth.inhomogeneous(d, 0.005, 0.12, seed=5)
+    smp = synth.sample(d, r, 300, seed=6)
+    ref = oracle.transfer(d, r, smp["syndromes"], threads=8)
+    logz, logp, cls = run(dev, d, chi, prec, smp["syndromes"], r)
+    err = check_logz(logz, ref, prec)
+    print("d=5 %s max |dlogZ| = %.3g" % (prec, err))
+    check_classes(cls, ref, BOUND[prec])
+
+
+def sparse_case(d, k, seed):
+    rng = np.random.default_rng(seed)
+    n = d * d
+    r0, c0 = rng.integers(0, d - 2, size=2)
+    cand = [(r0 + i) * d + (c0 + j) for i in range(3) for j in range(3)]
+    support = sorted(rng.choice(cand, size=k, replace=False).tolist())
+    rates = np.zeros((n, 3))
+    rates[support] = rng.uniform(0.02, 0.3, size=(k, 3))
+    errs = np.zeros((8, n), np.uint8)
+    errs[:, support] = rng.integers(0, 4, size=(8, k))
+    return rates, synth.syndromes_of(d, errs)
+
+
+@pytest.mark.parametrize("d,prec", [(9, "fp64"), (13, "fp64"), (17, "fp64"), (17, "fp32")])
+def test_sparse_support_exact_any_distance(dev, d, prec):
+    rates, syn = sparse_case(d, 6, seed=d)
+    ref = oracle.transfer(d, rates, syn, threads=8)
+    logz, _, cls = run(dev, d, 8, prec, syn, rates)
+    check_logz(logz, ref, prec)
+
+
+def test_impossible_and_trivial(dev):
+    d = 7
+    n, m = d * d, d * d - 1
+    rates = np.zeros((n, 3))
+    syn = np.zeros((3, m), np.uint8)
+    syn[1, 4] = 1
+    syn[2, m - 1] = 1
+    for prec in ("fp64", "fp32", "fp32plain"):
+        logz, logp, cls = run(dev, d, 8, prec, syn, rates)
+        assert abs(logz[0, 0]) < 1e-6 and np.isneginf(logz[0, 1:]).all()
+        assert np.isneginf(logz[1:]).all() and np.isneginf(logp[1:]).all()
+        assert (cls == 0).all() and not np.isnan(logz).any()
+
+
+def test_model_index_and_biased_noise(dev):
+    d = 5
+    rates = np.stack([synth.biased(d, 0.08, eta) for eta in (1.0, 10.0, 100.0)])
+    mi = (np.arange(120) % 3).astype(np.int32)
+    smp = synth.sample(d, rates, 120, seed=9, model_index=mi)
+    ref = np.concatenate([oracle.transfer(d, rates[k], smp["syndromes"][mi == k]) for k in range(3)])
+    order = np.concatenate([np.nonzero(mi == k)[0] for k in range(3)])
+    for prec in ("fp64", "fp32"):
+        logz, _, _ = run(dev, d, 16, prec, smp["syndromes"], rates, mi)
+        check_logz(logz[order], ref, prec)
+
+
+def test_truncated_d9_chi16_fp32(dev):
+    d = 9
+    r = synth.depolarizing(d, 0.11)
+    smp = synth.sample(d, r, 256, seed=2002)
+    ref = oracle.transfer(d, r, smp["syndromes"], threads=8)
+    logz, logp, cls = run(dev, d, 16, "fp32", smp["syndromes"], r)
+    err = abs_err(logz, ref)
+    print("d=9 chi=16 fp32 max |dlogZ| vs exact = %.3g" % err)
+    assert err < 1e-2
+    _, rcls = oracle.decide(ref)
+    assert (cls == rcls).mean() >= 0.99
+
+
+def test_deterministic_and_segment_independent(dev):
+    segs = []
+    ins = []
+    for d, chi in ((5, 8), (7, 12), (9, 16)):
+        r = synth.depolarizing(d, 0.1)
+        smp = synth.sample(d, r, 40, seed=d)
+        ins.append((d, chi, smp["syndromes"], r))
+        segs.append(tn.SegmentInput(d, chi, torch.from_numpy(smp["syndromes"]).to(dev),
+                                    torch.from_numpy(r).to(dev), None, "fp32"))
+    a = [o.logz.cpu().numpy() for o in tn.decode_segments(segs)]
+    b = [o.logz.cpu().numpy() for o in tn.decode_segments(segs)]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    for (d, chi, syn, r), x in zip(ins, a):
+        single, _, _ = run(dev, d, chi, "fp32", syn, r)
+        assert np.array_equal(single, x)

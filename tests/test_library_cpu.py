@@ -1,0 +1,74 @@
+"""Host-side checks of the C-ABI library that need no GPU."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+_lib = pytest.importorskip("paper_2605_17230_amd._lib")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libtnmld.so not built (run __graft_entry__.build())")
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _lib.header_functions()
+    assert {"tn_workspace_size", "tn_coset_loglik", "tn_decode_batch", "tn_coset_loglik_backward",
+            "tn_code_stabilizers", "tn_plan_info", "tn_last_error"} <= set(names)
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+@pytest.mark.parametrize("d", [3, 5, 9, 17, 21])
+def test_code_stabilizers_match_oracle_layout(d):
+    import paper_2605_17230_amd as tn
+    t, s = tn.code_stabilizers(d)
+    ot, os_ = oracle.layout(d)
+    assert np.array_equal(t, ot) and np.array_equal(s, os_)
+
+
+def _seg(**kw):
+    base = dict(d=5, chi=8, precision=1, n_models=1, rates=1, model_index=None, syndromes=1, count=4,
+                out_logz=1, out_logp=None, out_class=None)
+    base.update(kw)
+    return _lib.Segment(**base)
+
+
+@pytest.mark.parametrize("bad", [dict(d=4), dict(d=1), dict(d=33), dict(chi=-1), dict(precision=7),
+                                 dict(n_models=0), dict(count=-2), dict(syndromes=None), dict(out_logz=None)])
+def test_invalid_arguments_rejected_before_device(L, bad):
+    arr = (_lib.Segment * 1)(_seg(**bad))
+    rc = L.tn_coset_loglik(arr, 1, None, 0, None)
+    assert rc == _lib.TN_EINVAL
+    assert L.tn_last_error()
+    assert L.tn_workspace_size(arr, 1, 0) == 0
+
+
+def test_segment_count_limits(L):
+    arr = (_lib.Segment * 17)(*[_seg() for _ in range(17)])
+    assert L.tn_coset_loglik(arr, 17, None, 0, None) == _lib.TN_EINVAL
+    assert L.tn_coset_loglik(arr, 0, None, 0, None) == _lib.TN_EINVAL
+
+
+def test_no_device_reports_edevice(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    arr = (_lib.Segment * 1)(_seg())
+    assert L.tn_coset_loglik(arr, 1, None, 0, None) == _lib.TN_EDEVICE
+
+
+def test_plan_info_counts():
+    import paper_2605_17230_amd as tn
+    a = tn.plan_info(17, 32, "fp32")
+    b = tn.plan_info(17, 16, "fp32")
+    assert a["rows"] == 33 and a["flops"] > b["flops"] > 0
+    assert a["lds_bytes"] <= 160 * 1024
+    with pytest.raises(tn.TNError):
+        tn.plan_info(4, 8, "fp32")

@@ -79,7 +79,7 @@ __device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* 
   Real* C = reinterpret_cast<Real*>(smem + lay.C);
   Fac* Mm = reinterpret_cast<Fac*>(smem + lay.M);
   Fac* Vv = reinterpret_cast<Fac*>(smem + lay.V);
-  Real* Qs = reinterpret_cast<Real*>(smem + lay.Q);
+  Fac* Lt = reinterpret_cast<Fac*>(smem + lay.Lt);
   Fac* sig = reinterpret_cast<Fac*>(smem + lay.sig);
   __shared__ int s_flag;
   __shared__ int s_dead;
@@ -195,66 +195,90 @@ __device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* 
       __syncthreads();
       if (s_dead) break;
     }
-    // --- left-to-right: truncation ----------------------------------------
+    // --- left-to-right: QR of every site matrix, SVD where the bond is cut ----
     for (int J = 0; J < nsite; ++J) {
       const SiteStep st = row[J];
       const int qo = st.qo, k = st.k, kr = st.kr, Dl = st.Dl_new, Dn = st.Dr_new;
       const int nn = qo * kr, R = Dl * qo;
-      const int ldm = R + 1, ldv = kr + 1;
+      const int ldm = R + 1, ldl = kr + 1;
+      const int k2 = R < kr ? R : kr;  // rank of the site matrix
+      const bool cut = Dn < k2;
       Real* g = scr + region[J];
-      for (int e = tid; e < k * nn; e += NT) Qs[e] = g[e];
-      for (int e = tid; e < kr * kr; e += NT) Vv[(e / kr) * ldv + (e % kr)] = (e / kr == e % kr) ? Fac(1) : Fac(0);
-      __syncthreads();
-      // M[(l,so)][c] = sum_k C[l][k] Q[k][so][c], stored column-major
-      gemm_lds<Real>(Dl, nn, k, C, k, Qs, nn, [&](int i, int j, Real v) {
+      // M[(l,so)][c] = sum_k C[l][k] Q[k][so][c] (Q read from the site region),
+      // stored as M^T rows: Mm[c*ldm + (l,so)]
+      gemm_lds<Real>(Dl, nn, k, C, k, g, nn, [&](int i, int j, Real v) {
         const int so = j / kr, c = j % kr;
         Mm[c * ldm + i * qo + so] = Fac(v);
       });
       __syncthreads();
-      jacobi_svd<Fac>(Mm, R, kr, ldm, Vv, ldv, &s_flag);
-      // column norms and ranking
-      for (int c = tid; c < kr; c += NT) {
-        double s2 = 0;
-        for (int r = 0; r < R; ++r) s2 += (double)Mm[c * ldm + r] * (double)Mm[c * ldm + r];
-        sig[c] = Fac(sqrt(s2));
+      // M^T = Lf Qf (LQ), i.e. M = Qf^T Lf^T: a QR factorisation of M
+      lq_factor<Fac>(Mm, kr, R, ldm, tau, diag, dred);
+      // Lf (kr x k2) -> Lt, column-major (column j at Lt + j*ldl)
+      for (int e = tid; e < kr * k2; e += NT) {
+        const int r = e / k2, c = e % k2;
+        Lt[c * ldl + r] = c < r ? Mm[r * ldm + c] : (c == r ? diag[r] : Fac(0));
       }
       __syncthreads();
-      for (int c = tid; c < kr; c += NT) {
-        const Fac sc = sig[c];
-        int rank = 0;
-        for (int c2 = 0; c2 < kr; ++c2) {
-          const Fac s2 = sig[c2];
-          rank += (s2 > sc) || (s2 == sc && c2 < c);
+      lq_form_q<Fac>(Mm, kr, R, ldm, tau, vtmp);  // rows 0..k2-1 of Mm: Qf (k2 x R)
+      if (!cut) {
+        // A[(l,so)][r] = Qf[r][(l,so)], carry C[r][c] = Lf[c][r]
+        for (int e = tid; e < R * Dn; e += NT) {
+          const int lso = e / Dn, r = e % Dn;
+          g[e] = Real(Mm[r * ldm + lso]);
         }
-        perm[rank] = c;
-      }
-      __syncthreads();
-      if (J == nsite - 1) {
-        const double s0 = (double)sig[perm[0]];
-        if (!(s0 > TinyNorm<Fac>::v)) {
-          if (tid == 0) s_dead = 1;
-        } else {
-          logscale += log(s0);
+        for (int e = tid; e < Dn * kr; e += NT) {
+          const int r = e / kr, c = e % kr;
+          C[e] = Real(Lt[r * ldl + c]);
         }
+        __syncthreads();
+        if (J == nsite - 1) {
+          // last site: 1x1 carry = remaining norm (sign folded into the site)
+          const double l0 = (double)Lt[0];
+          if (!(fabs(l0) > TinyNorm<Fac>::v)) {
+            if (tid == 0) s_dead = 1;
+          } else {
+            logscale += log(fabs(l0));
+            if (l0 < 0.0)
+              for (int e = tid; e < R; e += NT) g[e] = -g[e];
+          }
+          __syncthreads();
+        }
+      } else {
+        // one-sided Jacobi on the columns of Lf: Lf W = U' S, so that
+        // M = (Qf^T W) S U'^T; keep the Dn largest singular values
+        for (int e = tid; e < k2 * k2; e += NT) Vv[(e / k2) * ldl + (e % k2)] = (e / k2 == e % k2) ? Fac(1) : Fac(0);
+        __syncthreads();
+        jacobi_svd<Fac>(Lt, kr, k2, ldl, Vv, ldl, SplitTol<Fac>::v, &s_flag);
+        for (int c = tid; c < k2; c += NT) {
+          double s2 = 0;
+          for (int r = 0; r < kr; ++r) s2 += (double)Lt[c * ldl + r] * (double)Lt[c * ldl + r];
+          sig[c] = Fac(sqrt(s2));
+        }
+        __syncthreads();
+        for (int c = tid; c < k2; c += NT) {
+          const Fac sc = sig[c];
+          int rank = 0;
+          for (int c2 = 0; c2 < k2; ++c2) {
+            const Fac s2 = sig[c2];
+            rank += (s2 > sc) || (s2 == sc && c2 < c);
+          }
+          perm[rank] = c;
+        }
+        __syncthreads();
+        // A[(l,so)][r] = sum_c Qf[c][(l,so)] W[c][perm r];  C[r][c'] = (Lf W)[c'][perm r]
+        for (int e = tid; e < R * Dn; e += NT) {
+          const int lso = e / Dn, r = e % Dn;
+          const Fac* w = Vv + perm[r] * ldl;
+          Fac acc = 0;
+          for (int c = 0; c < k2; ++c) acc += Mm[c * ldm + lso] * w[c];
+          g[e] = Real(acc);
+        }
+        for (int e = tid; e < Dn * kr; e += NT) {
+          const int r = e / kr, c = e % kr;
+          C[e] = Real(Lt[perm[r] * ldl + c]);
+        }
+        __syncthreads();
       }
-      // new site tensor A[l][so][r] and carry C[r][c'] = sigma_r V[c'][perm r];
-      // every singular value is kept (small ones of these graded matrices are
-      // accurate and can carry the weight of improbable cosets); only norms at
-      // the bottom of the real range count as zero
-      for (int e = tid; e < R * Dn; e += NT) {
-        const int lso = e / Dn, r = e % Dn;
-        const int c = perm[r];
-        const Fac sc = sig[c];
-        g[e] = Real((double)sc > TinyNorm<Fac>::v ? Mm[c * ldm + lso] / sc : Fac(0));
-      }
-      __syncthreads();
-      for (int e = tid; e < Dn * kr; e += NT) {
-        const int r = e / kr, c2 = e % kr;
-        const int c = perm[r];
-        const Fac sc = sig[c];
-        C[e] = Real((double)sc > TinyNorm<Fac>::v ? sc * Vv[c * ldv + c2] : Fac(0));
-      }
-      __syncthreads();
       if (s_dead) break;
     }
     if (s_dead) break;

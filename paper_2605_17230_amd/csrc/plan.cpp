@@ -229,12 +229,16 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
       h.max_m = std::max(h.max_m, (int)S.m);
       h.max_rows = std::max(h.max_rows, S.Dl_new * S.qo);
       h.max_bond = std::max({h.max_bond, (int)S.Dl_new, (int)S.Dr_new, (int)S.Dl_old, (int)S.Dr_old});
+      // counted work of the implemented algorithm (standard dense counts):
       double m = S.m, nn = (double)S.qo * S.kr;
+      double R = (double)S.Dl_new * S.qo, k2 = std::min(R, (double)S.kr);
       flops += 2.0 * S.Dl_old * S.qi * S.Dr_old * S.A * S.qo * S.B;  // MPO apply
-      flops += 2.0 * m * S.qo * rB * S.kr;                              // B . L
+      flops += 2.0 * m * S.qo * rB * S.kr;                              // (W A) . L
       flops += qr_flops(m, nn) + orgq_flops(nn, S.k);                  // LQ + explicit Q
       flops += 2.0 * S.Dl_new * S.k * nn;                               // C . Q
-      flops += svd_flops((double)S.Dl_new * S.qo, S.kr);                // truncation SVD
+      flops += qr_flops(R, S.kr) + orgq_flops(R, k2);                  // QR of the site matrix + Q
+      if (S.Dr_new < k2)                                                // bond truncated:
+        flops += svd_flops(S.kr, k2) + 2.0 * R * k2 * S.Dr_new;        //   SVD of R factor + A = Q W
     }
   }
   h.flops_fwd = flops;

@@ -106,10 +106,11 @@ void merge_maxima(PlanHeader* acc, const PlanHeader& h);
 // right-to-left phase (Aj, T, X, L, tau/diag/v) and the left-to-right phase
 // (C, M, V, Q, sig) are never live together and share storage.
 struct LdsLayout {
-  int32_t Aj, T, X, L, tau, diag, v;  // right-to-left phase
-  int32_t C, M, V, Q, sig;            // left-to-right phase
+  int32_t Aj, T, X, L;                // right-to-left phase
+  int32_t C, M, V, Lt, Q, sig;        // left-to-right phase
+  int32_t tau, diag, v;               // Householder scalars and reflector (both phases)
   int32_t W;                          // MPO values of the current site (<= 64, storage type)
-  int32_t red, perm, fbits, syn;      // FP64 reduction scratch, ranking, reference-error bits, syndrome
+  int32_t red, perm, rank, fbits, syn;  // FP64 reduction scratch, kept columns, column sets, reference-error bits, syndrome
   int32_t bytes;
 };
 
@@ -122,18 +123,20 @@ inline LdsLayout lds_layout(const PlanHeader& h, int rb, int fb) {
   o.T = p; p += pad64b((int64_t)h.max_T * rb);
   o.X = p; p += pad64b((int64_t)h.max_X * fb);
   o.L = p; p += pad64b((int64_t)h.max_L * rb);
-  o.tau = p; p += pad64b((int64_t)h.max_m * fb);
-  o.diag = p; p += pad64b((int64_t)h.max_m * fb);
-  o.v = p; p += pad64b((int64_t)h.max_n * fb);
   const int32_t rl_end = p;
   p = 0;
   o.C = p; p += pad64b((int64_t)h.max_C * rb);
   o.M = p; p += pad64b((int64_t)h.max_M * fb);
   o.V = p; p += pad64b((int64_t)h.max_V * fb);
-  o.Q = p; p += pad64b((int64_t)h.max_Q * rb);
+  o.Lt = p; p += pad64b((int64_t)h.max_V * fb);
   o.sig = p; p += pad64b((int64_t)(h.max_kr > h.max_bond ? h.max_kr : h.max_bond) * fb);
   const int32_t lr_end = p;
   p = rl_end > lr_end ? rl_end : lr_end;
+  const int32_t nh = h.max_m > h.max_kr ? h.max_m : h.max_kr;
+  const int32_t nv = h.max_n > h.max_rows ? h.max_n : h.max_rows;
+  o.tau = p; p += pad64b((int64_t)nh * fb);
+  o.diag = p; p += pad64b((int64_t)nh * fb);
+  o.v = p; p += pad64b((int64_t)nv * fb);
   o.W = p; p += pad64b(64 * rb);
   o.red = p; p += 64 * 8;
   o.perm = p; p += pad64b((int64_t)h.max_kr * 4);

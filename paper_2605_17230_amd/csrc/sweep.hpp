@@ -15,7 +15,7 @@
 
 namespace tnmld {
 
-constexpr int NT = 256;
+constexpr int NT = 512;
 constexpr int WAVE = 64;
 
 template <typename Real>
@@ -27,6 +27,19 @@ struct Eps<double> {
 template <>
 struct Eps<float> {
   static constexpr float v = 1.1920929e-07f;
+};
+// relative cosine between columns below which the SVD of a bond that is
+// being truncated is converged: the kept subspace is then exact to that
+// angle and the kept weight to its square
+template <typename Fac>
+struct SplitTol;
+template <>
+struct SplitTol<double> {
+  static constexpr double v = 1e-10;
+};
+template <>
+struct SplitTol<float> {
+  static constexpr double v = 1e-6;
 };
 // norms below this are treated as exact zeros (1/norm must stay finite in Real)
 template <typename Real>
@@ -183,18 +196,17 @@ __device__ void lq_form_q(Real* X, int m, int n, int ld, const Real* tau, Real* 
 // One-sided (Hestenes) Jacobi on the columns of M (rows x cols, column-major,
 // leading dimension ldm), accumulating the rotations in V (cols x cols,
 // column-major, ldv), which must hold the identity on entry.  Afterwards the
-// columns of M are mutually orthogonal: M_in V = M_out, and the column norms
-// are the singular values.  Parallel cyclic ordering (circle method): each
+// columns of M are mutually orthogonal to a relative cosine below tol:
+// M_in V = M_out, and the column norms are the singular values.  Parallel cyclic ordering (circle method): each
 // round rotates cols'/2 disjoint pairs, one pair per group of G lanes.
 template <typename Real>
-__device__ void jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv, int* flag) {
+__device__ void jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv, double tol, int* flag) {
   if (cols < 2) return;
   const int N = cols + (cols & 1);
   const int P = N >> 1;
   int G = WAVE;
   while (G > 1 && G * P > NT) G >>= 1;
   const int tid = threadIdx.x, g = tid / G, lane = tid % G;
-  const double tol = (double)Eps<Real>::v * (rows > 8 ? rows : 8);
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (tid == 0) *flag = 0;
     __syncthreads();

@@ -124,8 +124,16 @@ int tn_code_stabilizers(int32_t d, int32_t* type_out, int32_t* support_out);
 /* HOST helper: properties of the contraction plan for (d, chi, precision):
  * info[0] counted forward flops per (syndrome, coset), info[1] scratch bytes
  * per work-group, info[2] LDS bytes per work-group, info[3] sites per row,
- * info[4] rows, info[5] columns per site.  Returns TN_OK or a tn_status. */
+ * info[4] rows, info[5] columns per site, info[6] work-groups per CU.
+ * info: host array of >= 7 doubles.  Returns TN_OK or a tn_status. */
 int tn_plan_info(int32_t d, int32_t chi, int32_t precision, double* info);
+
+/* HOST helper: launch shape for (d, chi, precision) used by later calls in
+ * this process: group = lattice columns per MPS site (1 or 2; 0 = automatic),
+ * wg_per_cu = persistent work-groups per compute unit (1 or 2; 0 = as many as
+ * LDS allows).  group = wg_per_cu = 0 restores the default.  The autotuner
+ * sets these from its cache.  Returns TN_OK or TN_EINVAL. */
+int tn_set_tuning(int32_t d, int32_t chi, int32_t precision, int32_t group, int32_t wg_per_cu);
 
 /* Message for the last non-OK status returned on this thread. */
 const char* tn_last_error(void);

@@ -5,7 +5,14 @@ marshals arguments.  See include/tnmld.h for the C ABI.
 """
 from ._lib import TNError, lib, LIB_PATH  # noqa: F401
 from .api import (SegmentInput, SegmentOutput, code_stabilizers, coset_loglik, decode,  # noqa: F401
-                  decode_segments, plan_info)
+                  decode_segments, plan_info, set_tuning)
+
+from . import tune as _tune  # noqa: E402
+
+try:  # apply the autotuner's cached launch shapes (needs only the host library)
+    _tune.load(apply=True)
+except Exception:  # a missing or unreadable cache keeps the defaults
+    pass
 
 __all__ = ["TNError", "SegmentInput", "SegmentOutput", "coset_loglik", "decode", "decode_segments",
-           "plan_info", "code_stabilizers", "lib", "LIB_PATH"]
+           "plan_info", "set_tuning", "code_stabilizers", "lib", "LIB_PATH"]

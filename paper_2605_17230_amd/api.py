@@ -120,10 +120,15 @@ def coset_loglik(syndromes, rates, d, chi, precision="fp32", model_index=None):
 
 
 def plan_info(d, chi, precision="fp32"):
-    info = (ctypes.c_double * 6)()
+    info = (ctypes.c_double * 7)()
     check(lib().tn_plan_info(d, chi, PRECISIONS[precision], info))
     return dict(flops=info[0], scratch_bytes=info[1], lds_bytes=info[2], sites=int(info[3]),
-                rows=int(info[4]), group=int(info[5]))
+                rows=int(info[4]), group=int(info[5]), wg_per_cu=int(info[6]))
+
+
+def set_tuning(d, chi, precision, group=0, wg_per_cu=0):
+    """Launch shape for (d, chi, precision); zeros restore the default."""
+    check(lib().tn_set_tuning(d, chi, PRECISIONS[precision], group, wg_per_cu))
 
 
 def code_stabilizers(d):

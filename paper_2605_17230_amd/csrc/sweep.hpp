@@ -39,7 +39,7 @@ struct SplitTol<double> {
 };
 template <>
 struct SplitTol<float> {
-  static constexpr double v = 1e-6;
+  static constexpr double v = 1e-5;
 };
 // norms below this are treated as exact zeros (1/norm must stay finite in Real)
 template <typename Real>

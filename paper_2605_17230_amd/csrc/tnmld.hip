@@ -134,9 +134,33 @@ bool precision_built(int precision) {
 // largest usable LDS per block on gfx950 when no device is queried
 constexpr int kLdsLimit = 160 * 1024;
 
-// choose the column grouping: two columns per site when LDS allows
+constexpr int kLdsPerCU = 160 * 1024;
+constexpr int kMaxWgPerCU = 1024 / NT > 1 ? 1024 / NT : 1;  // <= 128 VGPRs: 4 waves per SIMD, 1024 threads per CU
+
+// Tuned launch shapes, set by tn_set_tuning (the autotuner's cache).
+struct Tune {
+  int group, wgs;
+};
+std::map<std::tuple<int, int, int>, Tune> g_tune;
+
+int wgs_for(int lds_bytes) {
+  const int w = kLdsPerCU / (lds_bytes + 256);
+  return w < 1 ? 0 : (w > kMaxWgPerCU ? kMaxWgPerCU : w);
+}
+
+// Choose the column grouping (1 or 2 columns per site): a tuned entry if one
+// exists, else the grouping that fits the most work-groups per CU (ties: 2).
 int choose_group(int d, int chi, int precision, int lds_limit, Plan* out, std::string* why) {
+  int forced = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tune.find(std::make_tuple(d, chi, precision));
+    if (it != g_tune.end()) forced = it->second.group;
+  }
+  int best_g = -1, best_w = 0;
+  Plan best;
   for (int g = 2; g >= 1; --g) {
+    if (forced && g != forced) continue;
     Plan p;
     std::string e = build_plan(d, chi, g, &p);
     if (!e.empty()) {
@@ -144,13 +168,19 @@ int choose_group(int d, int chi, int precision, int lds_limit, Plan* out, std::s
       return -1;
     }
     LdsLayout lay = lds_layout(p.h, real_bytes(precision), fac_bytes(precision));
-    if (lay.bytes <= lds_limit) {
-      *out = std::move(p);
-      return g;
+    if (lay.bytes > lds_limit) {
+      *why = "chi=" + std::to_string(chi) + " needs " + std::to_string(lay.bytes) + " B of LDS";
+      continue;
     }
-    *why = "chi=" + std::to_string(chi) + " needs " + std::to_string(lay.bytes) + " B of LDS";
+    const int w = wgs_for(lay.bytes);
+    if (w > best_w) {
+      best_w = w;
+      best_g = g;
+      best = std::move(p);
+    }
   }
-  return -1;
+  if (best_g > 0) *out = std::move(best);
+  return best_g;
 }
 
 int get_plan(int d, int chi, int precision, int lds_limit, DevPlan** out) {
@@ -202,6 +232,7 @@ struct Launch {
   JobTable jt;
   PlanHeader merged;
   int64_t scratch_elems;
+  int nwg;  // persistent work-groups of this launch
 };
 
 constexpr size_t kAlign = 256;
@@ -214,7 +245,7 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
   if (rc) return rc;
   DevInfo di;
   if ((rc = device_info(&di))) return rc;
-  *nwg = di.cus;  // one resident work-group per compute unit
+  *nwg = 0;
   // order segments: larger d first so the heaviest items start first
   std::vector<int> order(nseg);
   for (int i = 0; i < nseg; ++i) order[i] = i;
@@ -242,14 +273,27 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
       items += 4 * s.count;
       merge_maxima(&L.merged, dp->plan.h);
       L.scratch_elems = std::max<int64_t>(L.scratch_elems, dp->plan.h.scratch_elems);
+      int tw = 0;
+      {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_tune.find(std::make_tuple(s.d, s.chi, prec));
+        if (it != g_tune.end()) tw = it->second.wgs;
+      }
+      if (tw > 0) L.nwg = L.nwg ? std::min(L.nwg, tw) : tw;  // per-CU count for now
     }
     L.jt.nitems = items;
     if (L.jt.n > 0) out->push_back(L);
   }
   size_t bytes = align_up(sizeof(unsigned long long) * 4);
   for (auto& L : *out) {
-    if (L.merged.max_bond > NT) return fail(TN_EUNSUPPORTED, "bond dimension above 256");
-    bytes += (size_t)*nwg * align_up((size_t)L.scratch_elems * real_bytes(L.precision));
+    if (L.merged.max_bond > NT) return fail(TN_EUNSUPPORTED, "bond dimension above the work-group size");
+    const int lb = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision)).bytes;
+    int w = wgs_for(lb);
+    if (L.nwg > 0) w = std::min(w, L.nwg);
+    if (w < 1) return fail(TN_EUNSUPPORTED, "LDS of the merged plans exceeds one CU");
+    L.nwg = w * di.cus;
+    *nwg = std::max(*nwg, L.nwg);
+    bytes += (size_t)L.nwg * align_up((size_t)L.scratch_elems * real_bytes(L.precision));
   }
   *ws_bytes = bytes;
   return TN_OK;
@@ -287,10 +331,10 @@ int run_forward(const tn_segment* segs, int32_t nseg, void* workspace, size_t ws
   for (auto& L : launches) {
     unsigned long long* counter = reinterpret_cast<unsigned long long*>(base) + li;
     char* scr = base + off;
-    off += (size_t)nwg * align_up((size_t)L.scratch_elems * real_bytes(L.precision));
-    if (L.precision == TN_FP64) rc = launch_fwd<double, double>(L, nwg, scr, counter, st);
-    else if (L.precision == TN_FP32) rc = launch_fwd<float, double>(L, nwg, scr, counter, st);
-    else rc = launch_fwd<float, float>(L, nwg, scr, counter, st);
+    off += (size_t)L.nwg * align_up((size_t)L.scratch_elems * real_bytes(L.precision));
+    if (L.precision == TN_FP64) rc = launch_fwd<double, double>(L, L.nwg, scr, counter, st);
+    else if (L.precision == TN_FP32) rc = launch_fwd<float, double>(L, L.nwg, scr, counter, st);
+    else rc = launch_fwd<float, float>(L, L.nwg, scr, counter, st);
     if (rc) return rc;
     ++li;
   }
@@ -390,6 +434,22 @@ int tn_plan_info(int32_t d, int32_t chi, int32_t precision, double* info) {
   info[3] = p.h.nsite;
   info[4] = p.h.nstep;
   info[5] = g;
+  info[6] = wgs_for((int)info[2]);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tune.find(std::make_tuple(d, chi, precision));
+    if (it != g_tune.end() && it->second.wgs > 0) info[6] = std::min<double>(info[6], it->second.wgs);
+  }
+  return TN_OK;
+}
+
+int tn_set_tuning(int32_t d, int32_t chi, int32_t precision, int32_t group, int32_t wg_per_cu) {
+  if (d < 3 || d > TN_MAX_D || d % 2 == 0 || chi < 0 || precision < TN_FP64 || precision > TN_FP32_PLAIN ||
+      group < 0 || group > 2 || wg_per_cu < 0 || wg_per_cu > kMaxWgPerCU)
+    return fail(TN_EINVAL, "bad tuning arguments");
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (group == 0 && wg_per_cu == 0) g_tune.erase(std::make_tuple(d, chi, precision));
+  else g_tune[std::make_tuple(d, chi, precision)] = Tune{group, wg_per_cu};
   return TN_OK;
 }
 

@@ -4,8 +4,8 @@ The contraction runs in ``libtnmld.so`` (HIP, gfx950); this package only
 marshals arguments.  See include/tnmld.h for the C ABI.
 """
 from ._lib import TNError, lib, LIB_PATH  # noqa: F401
-from .api import (SegmentInput, SegmentOutput, code_stabilizers, coset_loglik, decode,  # noqa: F401
-                  decode_segments, plan_info, set_tuning)
+from .api import (SegmentInput, SegmentOutput, code_stabilizers, coset_loglik, coset_loglik_backward,  # noqa: F401
+                  decode, decode_segments, log_posterior, plan_info, set_tuning)
 
 from . import tune as _tune  # noqa: E402
 
@@ -14,5 +14,5 @@ try:  # apply the autotuner's cached launch shapes (needs only the host library)
 except Exception:  # a missing or unreadable cache keeps the defaults
     pass
 
-__all__ = ["TNError", "SegmentInput", "SegmentOutput", "coset_loglik", "decode", "decode_segments",
+__all__ = ["TNError", "SegmentInput", "SegmentOutput", "coset_loglik", "coset_loglik_backward", "log_posterior", "decode", "decode_segments",
            "plan_info", "set_tuning", "code_stabilizers", "lib", "LIB_PATH"]

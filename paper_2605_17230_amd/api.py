@@ -119,6 +119,64 @@ def coset_loglik(syndromes, rates, d, chi, precision="fp32", model_index=None):
     return outs[0].logz, outs[0].logp
 
 
+def coset_loglik_backward(segs, grad_logp, stream=None):
+    """d (sum_b grad_logp[b] log P(s_b)) / d ln rates for each segment.
+
+    grad_logp: list of float64 [B] device tensors, one per segment.  Returns
+    (outputs, grads) with grads[i] float64 [M, d*d, 3] (a fresh zeroed tensor
+    that the library accumulates into)."""
+    arr, outs, keep = _prepare(segs)
+    L = lib()
+    nbytes = L.tn_workspace_size(arr, len(segs), 1)
+    if nbytes == 0:
+        check(_lib.TN_EINVAL if not L.tn_last_error() else -1)
+    dev = segs[0].syndromes.device
+    ws = workspace(nbytes, dev)
+    gp = [g.to(device=dev, dtype=torch.float64).contiguous() for g in grad_logp]
+    grads = []
+    for s, g in zip(segs, gp):
+        m = s.rates.shape[0] if s.rates.dim() == 3 else 1
+        if g.shape != (s.syndromes.shape[0],):
+            raise ValueError("grad_logp[i] must be [B]")
+        grads.append(torch.zeros((m, s.d * s.d, 3), dtype=torch.float64, device=dev))
+    gp_arr = (ctypes.c_void_p * len(segs))(*[g.data_ptr() for g in gp])
+    gr_arr = (ctypes.c_void_p * len(segs))(*[g.data_ptr() for g in grads])
+    st = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    check(L.tn_coset_loglik_backward(arr, len(segs), gp_arr, gr_arr, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                     ctypes.c_void_p(st)))
+    del keep
+    return outs, grads
+
+
+class _LogPosterior(torch.autograd.Function):
+    """log P(s_b) as a function of theta = ln rates; the backward is the
+    library's adjoint contraction."""
+
+    @staticmethod
+    def forward(ctx, log_rates, syndromes, model_index, d, chi, precision):
+        rates = log_rates.detach().exp()
+        seg = SegmentInput(d, chi, syndromes, rates, model_index, precision)
+        o = decode_segments([seg])[0]
+        ctx.seg = seg
+        ctx.rates_dim = log_rates.dim()
+        ctx.mark_non_differentiable(o.logz)
+        return o.logp, o.logz
+
+    @staticmethod
+    def backward(ctx, g_logp, g_logz):
+        if g_logz is not None and bool((g_logz != 0).any()):
+            raise NotImplementedError("only log P(s) is differentiable")
+        _, grads = coset_loglik_backward([ctx.seg], [g_logp])
+        g = grads[0] if ctx.rates_dim == 3 else grads[0][0]
+        return g, None, None, None, None, None
+
+
+def log_posterior(log_rates, syndromes, d, chi, precision="fp32", model_index=None):
+    """(log P(s) [B], log Z [B, 4]) with autograd through log_rates
+    ([d*d, 3] or [M, d*d, 3] float64 = ln p_{q,X|Y|Z})."""
+    return _LogPosterior.apply(log_rates, syndromes, model_index, d, chi, precision)
+
+
 def plan_info(d, chi, precision="fp32"):
     info = (ctypes.c_double * 7)()
     check(lib().tn_plan_info(d, chi, PRECISIONS[precision], info))

@@ -20,8 +20,11 @@ struct JobDev {
   const int32_t* model_index;
   const uint8_t* syn;
   double* logz;
+  const double* logp;   // backward: log P(s) of the forward pass
+  const double* gradp;  // backward: d loss / d log P(s)
   int64_t count;
   int64_t item_begin;
+  int64_t part_ofs;     // backward: offset of this segment in a work-group's partial gradient
   int32_t n_models;
   int32_t pad;
 };
@@ -49,47 +52,70 @@ __device__ inline Real pauli_weight(const double* rq, int fb, int P) {
 // Forward contraction of one item; returns log Z (FP64).  Writes the class
 // index of the coset into *label.  Collective over the work-group.
 // Real: type of the MPS in HBM, of the MPO values and of the GEMM operands;
-// Fac: type of the LQ / SVD factorisations (LDS).
+// Fac: type of the LQ / SVD factorisations (LDS);
+// GM: how the two contraction GEMMs run: GEMM_VALU (Real arithmetic),
+// GEMM_BF16 (bf16 MFMA, FP32 accumulation) or GEMM_BF16X3 (split bf16).
+enum { GEMM_VALU = 0, GEMM_BF16 = 1, GEMM_BF16X3 = 2 };
+
+template <int GM, typename Real, typename AL, typename BL, typename ST>
+__device__ inline void contract_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb, AL, BL,
+                                     ST store) {
+  if constexpr (GM == GEMM_VALU) {
+    gemm_lds<Real>(M, N, K, A, lda, B, ldb, store);
+  } else {
+#ifndef TNMLD_EMU
+    gemm_mfma_bf16<GM == GEMM_BF16X3>(
+        M, N, K, [&](int i, int k) { return (float)A[i * lda + k]; }, [&](int k, int j) { return (float)B[k * ldb + j]; },
+        store);
+#endif
+  }
+}
+
+// LDS work areas of the sweep, carved from the dynamic shared memory.
 template <typename Real, typename Fac>
-__device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* smem, const LdsLayout& lay,
-                               Real* scr, int* label) {
-  const uint8_t* plan = job.plan;
-  const PlanHeader* H = reinterpret_cast<const PlanHeader*>(plan);
-  const int d = H->d, n = H->n, m = H->m, nsite = H->nsite, nstep = H->nstep;
-  const SiteStep* steps = reinterpret_cast<const SiteStep*>(plan + H->steps_ofs);
-  const uint8_t* codes = plan + H->codes_ofs;
-  const CheckDesc* checks = reinterpret_cast<const CheckDesc*>(plan + H->checks_ofs);
-  const int64_t* region = reinterpret_cast<const int64_t*>(plan + H->region_ofs);
-  const uint8_t* init_qi = plan + H->init_qi_ofs;
-  const int16_t* fin = reinterpret_cast<const int16_t*>(plan + H->final_ofs);
-  const int tid = threadIdx.x;
+struct Work {
+  uint8_t* fbits;
+  uint8_t* syn;
+  int* perm;
+  double* dred;
+  Real *Wv, *Aj, *T, *L, *C;
+  Fac *X, *tau, *diag, *vtmp, *Mm, *Vv, *Lt, *sig;
+  int* s_flag;
+  int* s_dead;
+};
 
-  uint8_t* fbits = smem + lay.fbits;
-  uint8_t* syn = smem + lay.syn;
-  int* perm = reinterpret_cast<int*>(smem + lay.perm);
-  double* dred = reinterpret_cast<double*>(smem + lay.red);
-  Real* Wv = reinterpret_cast<Real*>(smem + lay.W);
-  Real* Aj = reinterpret_cast<Real*>(smem + lay.Aj);
-  Real* T = reinterpret_cast<Real*>(smem + lay.T);
-  Fac* X = reinterpret_cast<Fac*>(smem + lay.X);
-  Real* L = reinterpret_cast<Real*>(smem + lay.L);
-  Fac* tau = reinterpret_cast<Fac*>(smem + lay.tau);
-  Fac* diag = reinterpret_cast<Fac*>(smem + lay.diag);
-  Fac* vtmp = reinterpret_cast<Fac*>(smem + lay.v);
-  Real* C = reinterpret_cast<Real*>(smem + lay.C);
-  Fac* Mm = reinterpret_cast<Fac*>(smem + lay.M);
-  Fac* Vv = reinterpret_cast<Fac*>(smem + lay.V);
-  Fac* Lt = reinterpret_cast<Fac*>(smem + lay.Lt);
-  Fac* sig = reinterpret_cast<Fac*>(smem + lay.sig);
-  __shared__ int s_flag;
-  __shared__ int s_dead;
-  __shared__ int s_label;
+template <typename Real, typename Fac>
+__device__ inline Work<Real, Fac> carve(uint8_t* smem, const LdsLayout& lay, int* flags) {
+  Work<Real, Fac> w;
+  w.fbits = smem + lay.fbits;
+  w.syn = smem + lay.syn;
+  w.perm = reinterpret_cast<int*>(smem + lay.perm);
+  w.dred = reinterpret_cast<double*>(smem + lay.red);
+  w.Wv = reinterpret_cast<Real*>(smem + lay.W);
+  w.Aj = reinterpret_cast<Real*>(smem + lay.Aj);
+  w.T = reinterpret_cast<Real*>(smem + lay.T);
+  w.L = reinterpret_cast<Real*>(smem + lay.L);
+  w.C = reinterpret_cast<Real*>(smem + lay.C);
+  w.X = reinterpret_cast<Fac*>(smem + lay.X);
+  w.tau = reinterpret_cast<Fac*>(smem + lay.tau);
+  w.diag = reinterpret_cast<Fac*>(smem + lay.diag);
+  w.vtmp = reinterpret_cast<Fac*>(smem + lay.v);
+  w.Mm = reinterpret_cast<Fac*>(smem + lay.M);
+  w.Vv = reinterpret_cast<Fac*>(smem + lay.V);
+  w.Lt = reinterpret_cast<Fac*>(smem + lay.Lt);
+  w.sig = reinterpret_cast<Fac*>(smem + lay.sig);
+  w.s_flag = flags;
+  w.s_dead = flags + 1;
+  return w;
+}
 
-  const int model = job.model_index ? job.model_index[b] : 0;
-  const double* rates = job.rates + (int64_t)model * n * 3;
-
-  // --- 1. reference error -------------------------------------------------
-  for (int j = tid; j < m; j += NT) syn[j] = job.syn[b * m + j];
+// Reference error of coset mlog (paper Sec. 3.2.1: the representative
+// E_{l,s} whose stabiliser multiples are summed): fbits[q] = (x | z << 1) of
+// R(s) * L_m.  Returns the class index the result belongs to.  Collective.
+__device__ inline int prep_reference(const PlanHeader* H, const CheckDesc* checks, const uint8_t* syn_g, int mlog,
+                                     uint8_t* syn, uint8_t* fbits, int* s_label) {
+  const int d = H->d, n = H->n, m = H->m, tid = threadIdx.x;
+  for (int j = tid; j < m; j += NT) syn[j] = syn_g[j];
   __syncthreads();
   for (int q = tid; q < n; q += NT) {
     const int r = q / d, c = q % d;
@@ -113,8 +139,7 @@ __device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* 
     // logical representatives: X on column lx_col has class X (it crosses row 0
     // once), Z on row lz_row has class Z (it crosses column 0 once)
     const int lx = (mlog == 1 || mlog == 2), lz = (mlog == 2 || mlog == 3);
-    s_label = pauli_code(a ^ lx, bb ^ lz);
-    s_dead = 0;
+    *s_label = pauli_code(a ^ lx, bb ^ lz);
   }
   __syncthreads();
   for (int q = tid; q < n; q += NT) {
@@ -124,18 +149,36 @@ __device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* 
     if ((mlog == 2 || mlog == 3) && r == H->lz_row) fb ^= 2;
     fbits[q] = (uint8_t)fb;
   }
-  *label = s_label;
-
-  // --- initial MPS: product of all-ones vectors ------------------------------
-  for (int J = 0; J < nsite; ++J) {
-    const int qi = init_qi[J];
-    for (int e = tid; e < qi; e += NT) scr[region[J] + e] = Real(1);
-  }
   __syncthreads();
+  return *s_label;
+}
 
-  double logscale = 0.0;
-  for (int u = 0; u < nstep; ++u) {
-    const SiteStep* row = steps + (int64_t)u * nsite;
+// All-ones product state: site J is 1 x dims[J] x 1.  Collective.
+template <typename Real>
+__device__ inline void mps_ones(Real* scr, const int64_t* region, const uint8_t* dims, int nsite) {
+  for (int J = 0; J < nsite; ++J)
+    for (int e = threadIdx.x; e < dims[J]; e += NT) scr[region[J] + e] = Real(1);
+  __syncthreads();
+}
+
+// One row of the boundary-MPS sweep on the MPS stored at scr + region[J]:
+// apply the row MPO (transposed when row[J].tr), bring the product to
+// right-canonical form (right-to-left LQ), then move the centre back
+// left-to-right by QR, truncating the bonds the plan cuts by SVD.  The MPS is
+// left normalised; log-norms go to `logscale`.  Returns false when the state
+// vanished (the coset has probability zero).  Collective.
+template <typename Real, typename Fac, int GM>
+__device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, const double* rates, Real* scr,
+                         const int64_t* region, Work<Real, Fac>& w, double& logscale) {
+  const int tid = threadIdx.x;
+  uint8_t* fbits = w.fbits;
+  int* perm = w.perm;
+  double* dred = w.dred;
+  Real *Wv = w.Wv, *Aj = w.Aj, *T = w.T, *L = w.L, *C = w.C;
+  Fac *X = w.X, *tau = w.tau, *diag = w.diag, *vtmp = w.vtmp, *Mm = w.Mm, *Vv = w.Vv, *Lt = w.Lt, *sig = w.sig;
+  if (tid == 0) w.s_dead[0] = 0;
+  __syncthreads();
+  do {
     // --- right-to-left: MPO apply + LQ --------------------------------------
     if (tid == 0) L[0] = Real(1);
     __syncthreads();
@@ -147,7 +190,13 @@ __device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* 
       const int ncode = A * qi * qo * B;
       const uint8_t* cd = codes + st.wofs;
       if (tid < ncode) {
-        const int c = cd[tid];
+        // plan order [a][si][so][b]; a transposed row reads the forward code [a][so][si][b]
+        int ci = tid;
+        if (st.tr) {
+          const int bb = tid % B, so = (tid / B) % qo, si = (tid / (B * qo)) % qi, a = tid / (B * qo * qi);
+          ci = ((a * qo + so) * qi + si) * B + bb;
+        }
+        const int c = cd[ci];
         Real v = Real(0);
         if (c == W_ONE) v = Real(1);
         else if (c >= W_PAULI) v = pauli_weight<Real>(rates + 3 * st.q, fbits[st.q], c - W_PAULI);
@@ -168,7 +217,8 @@ __device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* 
         }
         __syncthreads();
         // X[:, so*kr + c] = T . L
-        gemm_lds<Real>(mJ, kr, RB, T, RB, L, kr, [&](int i, int j, Real v) { X[i * nn + so * kr + j] = Fac(v); });
+        contract_gemm<GM, Real>(mJ, kr, RB, T, RB, L, kr, 0, 0,
+                                [&](int i, int j, Real v) { X[i * nn + so * kr + j] = Fac(v); });
         __syncthreads();
       }
       lq_factor<Fac>(X, mJ, nn, nn, tau, diag, dred);
@@ -187,13 +237,13 @@ __device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* 
       const Real l0 = L[0];
       __syncthreads();
       if (!(fabs((double)l0) > 0.0)) {
-        if (tid == 0) s_dead = 1;
+        if (tid == 0) w.s_dead[0] = 1;
       } else {
         logscale += log(fabs((double)l0));
         if (tid == 0) C[0] = l0 > Real(0) ? Real(1) : Real(-1);
       }
       __syncthreads();
-      if (s_dead) break;
+      if (w.s_dead[0]) break;
     }
     // --- left-to-right: QR of every site matrix, SVD where the bond is cut ----
     for (int J = 0; J < nsite; ++J) {
@@ -206,7 +256,7 @@ __device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* 
       Real* g = scr + region[J];
       // M[(l,so)][c] = sum_k C[l][k] Q[k][so][c] (Q read from the site region),
       // stored as M^T rows: Mm[c*ldm + (l,so)]
-      gemm_lds<Real>(Dl, nn, k, C, k, g, nn, [&](int i, int j, Real v) {
+      contract_gemm<GM, Real>(Dl, nn, k, C, k, g, nn, 0, 0, [&](int i, int j, Real v) {
         const int so = j / kr, c = j % kr;
         Mm[c * ldm + i * qo + so] = Fac(v);
       });
@@ -235,7 +285,7 @@ __device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* 
           // last site: 1x1 carry = remaining norm (sign folded into the site)
           const double l0 = (double)Lt[0];
           if (!(fabs(l0) > TinyNorm<Fac>::v)) {
-            if (tid == 0) s_dead = 1;
+            if (tid == 0) w.s_dead[0] = 1;
           } else {
             logscale += log(fabs(l0));
             if (l0 < 0.0)
@@ -248,7 +298,7 @@ __device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* 
         // M = (Qf^T W) S U'^T; keep the Dn largest singular values
         for (int e = tid; e < k2 * k2; e += NT) Vv[(e / k2) * ldl + (e % k2)] = (e / k2 == e % k2) ? Fac(1) : Fac(0);
         __syncthreads();
-        jacobi_svd<Fac>(Lt, kr, k2, ldl, Vv, ldl, SplitTol<Fac>::v, &s_flag);
+        jacobi_svd<Fac>(Lt, kr, k2, ldl, Vv, ldl, SplitTol<Fac>::v, w.s_flag);
         for (int c = tid; c < k2; c += NT) {
           double s2 = 0;
           for (int r = 0; r < kr; ++r) s2 += (double)Lt[c * ldl + r] * (double)Lt[c * ldl + r];
@@ -279,19 +329,23 @@ __device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* 
         }
         __syncthreads();
       }
-      if (s_dead) break;
+      if (w.s_dead[0]) break;
     }
-    if (s_dead) break;
-  }
-  if (s_dead) return -INFINITY;
+  } while (0);
+  const bool alive = !w.s_dead[0];
+  __syncthreads();
+  return alive;
+}
 
-  // --- close: sum every remaining variable --------------------------------
-  double* vv = reinterpret_cast<double*>(smem + lay.red);
-  Fac* vacc = sig;
+// Sum of the MPS over every physical index (the closing all-ones boundary);
+// returns log of it (FP64), -inf when not positive.  Collective.
+template <typename Real, typename Fac>
+__device__ inline double mps_close(const Real* scr, const int64_t* region, const int16_t* dims, int nsite, Fac* vacc) {
+  const int tid = threadIdx.x;
   if (tid == 0) vacc[0] = Fac(1);
   __syncthreads();
   for (int J = 0; J < nsite; ++J) {
-    const int Dl = fin[3 * J], qo = fin[3 * J + 1], Dr = fin[3 * J + 2];
+    const int Dl = dims[3 * J], qo = dims[3 * J + 1], Dr = dims[3 * J + 2];
     const Real* g = scr + region[J];
     Fac acc = 0;
     if (tid < Dr)
@@ -304,9 +358,36 @@ __device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* 
     if (tid < Dr) vacc[tid] = acc;
     __syncthreads();
   }
-  (void)vv;
   const double tot = (double)vacc[0];
-  return tot > 0.0 ? logscale + log(tot) : -INFINITY;
+  __syncthreads();
+  return tot > 0.0 ? log(tot) : -INFINITY;
+}
+
+// Forward contraction of one (syndrome b, coset mlog): log Z (FP64); *label
+// receives the class the coset belongs to.  Collective.
+template <typename Real, typename Fac, int GM = GEMM_VALU>
+__device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* smem, const LdsLayout& lay,
+                               Real* scr, int* label) {
+  const uint8_t* plan = job.plan;
+  const PlanHeader* H = reinterpret_cast<const PlanHeader*>(plan);
+  const int n = H->n, m = H->m, nsite = H->nsite, nstep = H->nstep;
+  const SiteStep* steps = reinterpret_cast<const SiteStep*>(plan + H->steps_ofs);
+  const uint8_t* codes = plan + H->codes_ofs;
+  const CheckDesc* checks = reinterpret_cast<const CheckDesc*>(plan + H->checks_ofs);
+  const int64_t* region = reinterpret_cast<const int64_t*>(plan + H->region_ofs);
+  __shared__ int s_flags[2];
+  __shared__ int s_label;
+  Work<Real, Fac> w = carve<Real, Fac>(smem, lay, s_flags);
+  const int model = job.model_index ? job.model_index[b] : 0;
+  const double* rates = job.rates + (int64_t)model * n * 3;
+  *label = prep_reference(H, checks, job.syn + b * m, mlog, w.syn, w.fbits, &s_label);
+  mps_ones(scr, region, plan + H->init_qi_ofs, nsite);
+  double logscale = 0.0;
+  for (int u = 0; u < nstep; ++u)
+    if (!row_step<Real, Fac, GM>(steps + (int64_t)u * nsite, nsite, codes, rates, scr, region, w, logscale))
+      return -INFINITY;
+  const int16_t* fin = reinterpret_cast<const int16_t*>(plan + H->final_ofs);
+  return logscale + mps_close<Real, Fac>(scr, region, fin, nsite, w.sig);
 }
 
 }  // namespace tnmld

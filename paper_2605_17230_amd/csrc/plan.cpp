@@ -243,6 +243,107 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
   }
   h.flops_fwd = flops;
 
+  // --- bottom-up sweep (adjoint): the transposed row MPOs applied from the
+  // last row upwards to the all-ones closing state; same bond bookkeeping ---
+  std::vector<SiteStep> bu((size_t)nstep * nsite);
+  {
+    std::vector<int> Db(nsite + 1, 1);
+    for (int s2 = 0; s2 < nstep; ++s2) {
+      const int u = nstep - 1 - s2;
+      for (int J = 0; J < nsite; ++J) {
+        SiteStep S = steps[(size_t)u * nsite + J];
+        std::swap(S.qi, S.qo);
+        S.tr = 1;
+        bu[(size_t)s2 * nsite + J] = S;
+      }
+      std::vector<int> kk(nsite + 1, 1);
+      for (int J = nsite - 1; J >= 0; --J) {
+        SiteStep& S = bu[(size_t)s2 * nsite + J];
+        int Dl = J > 0 ? Db[J - 1] : 1, Dr = J + 1 < nsite ? Db[J] : 1;
+        int mJ = Dl * S.A, kr = kk[J + 1], k = std::min(mJ, (int)S.qo * kr);
+        kk[J] = k;
+        S.Dl_old = (int16_t)Dl;
+        S.Dr_old = (int16_t)Dr;
+        S.m = (int16_t)mJ;
+        S.kr = (int16_t)kr;
+        S.k = (int16_t)k;
+      }
+      int Dl = 1;
+      for (int J = 0; J < nsite; ++J) {
+        SiteStep& S = bu[(size_t)s2 * nsite + J];
+        int Dr = std::min(Dl * (int)S.qo, (int)S.kr);
+        if (chi > 0) Dr = std::min(Dr, chi);
+        if (J == nsite - 1) Dr = 1;
+        S.Dl_new = (int16_t)Dl;
+        S.Dr_new = (int16_t)Dr;
+        Db[J] = Dr;
+        Dl = Dr;
+      }
+    }
+  }
+  std::vector<int16_t> bu_fin((size_t)nsite * 3);
+  for (int J = 0; J < nsite; ++J) {
+    const SiteStep& S = bu[(size_t)(nstep - 1) * nsite + J];
+    bu_fin[3 * J] = S.Dl_new;
+    bu_fin[3 * J + 1] = S.qo;
+    bu_fin[3 * J + 2] = S.Dr_new;
+  }
+  // sizes covering both sweeps; truncated-MPS and environment sizes
+  int64_t mps_max = 0, env_max = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const std::vector<SiteStep>& V = pass == 0 ? steps : bu;
+    for (int u = 0; u < nstep; ++u) {
+      int64_t mps = 0;
+      for (int J = 0; J < nsite; ++J) {
+        const SiteStep& S = V[(size_t)u * nsite + J];
+        int64_t sz = std::max<int64_t>({(int64_t)S.k * S.qo * S.kr, (int64_t)S.Dl_new * S.qo * S.Dr_new,
+                                        (int64_t)S.Dl_old * S.qi * S.Dr_old});
+        region[J] = std::max(region[J], sz);
+        mps += std::max<int64_t>((int64_t)S.Dl_new * S.qo * S.Dr_new, (int64_t)S.Dl_old * S.qi * S.Dr_old);
+        int rB = S.Dr_old * S.B;
+        h.max_Aj = std::max(h.max_Aj, S.Dl_old * S.qi * S.Dr_old);
+        h.max_T = std::max(h.max_T, S.m * rB);
+        h.max_X = std::max(h.max_X, S.m * S.qo * S.kr);
+        h.max_L = std::max({h.max_L, S.m * S.k, rB * S.kr});
+        h.max_C = std::max(h.max_C, S.Dl_new * S.k);
+        h.max_M = std::max(h.max_M, (S.Dl_new * S.qo + 1) * S.kr);
+        h.max_V = std::max(h.max_V, (S.kr + 1) * S.kr);
+        h.max_Q = std::max(h.max_Q, S.k * S.qo * S.kr);
+        h.max_kr = std::max(h.max_kr, (int)S.kr);
+        h.max_n = std::max(h.max_n, S.qo * S.kr);
+        h.max_m = std::max(h.max_m, (int)S.m);
+        h.max_rows = std::max(h.max_rows, S.Dl_new * S.qo);
+        h.max_bond = std::max({h.max_bond, (int)S.Dl_new, (int)S.Dr_new, (int)S.Dl_old, (int)S.Dr_old});
+      }
+      mps_max = std::max(mps_max, mps);
+    }
+  }
+  // environments of row u: E_J / R_J over (top bond, MPO bond, bottom bond)
+  for (int u = 0; u < nstep; ++u) {
+    int64_t env = 0;
+    for (int J = 0; J <= nsite; ++J) {
+      // bond between J-1 and J: top = fwd row u input bonds, bottom = bu row (nstep-1-u) input bonds
+      const SiteStep& T = steps[(size_t)u * nsite + std::min(J, nsite - 1)];
+      const SiteStep& Bv = bu[(size_t)(nstep - 1 - u) * nsite + std::min(J, nsite - 1)];
+      int dt = J == nsite ? 1 : T.Dl_old, db = J == nsite ? 1 : Bv.Dl_old, a = J == nsite ? 1 : T.A;
+      env += (int64_t)dt * a * db;
+    }
+    env_max = std::max(env_max, env);
+  }
+  int64_t tmp_max = 64;
+  for (int u = 0; u < nstep; ++u)
+    for (int J = 0; J < nsite; ++J) {
+      const SiteStep& T = steps[(size_t)u * nsite + J];
+      const SiteStep& Bv = bu[(size_t)(nstep - 1 - u) * nsite + J];
+      const int64_t DlF = Bv.Dl_old;
+      tmp_max = std::max<int64_t>({tmp_max, (int64_t)T.A * DlF * T.qi * T.Dr_old, DlF * T.qo * T.B * T.Dr_old,
+                                   DlF * T.qi * T.A * T.Dr_old});
+    }
+  h.tmp_elems = (tmp_max + 63) / 64 * 64;
+  h.mps_elems = (mps_max + 63) / 64 * 64;
+  h.env_elems = (2 * env_max + 63) / 64 * 64;
+
+
   // final MPS shape per site
   std::vector<int16_t> fin((size_t)nsite * 3);
   for (int J = 0; J < nsite; ++J) {
@@ -299,6 +400,10 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
   off = align8(off + init_qi.size());
   h.final_ofs = (int32_t)off;
   off = align8(off + fin.size() * sizeof(int16_t));
+  h.bu_steps_ofs = (int32_t)off;
+  off = align8(off + bu.size() * sizeof(SiteStep));
+  h.bu_final_ofs = (int32_t)off;
+  off = align8(off + bu_fin.size() * sizeof(int16_t));
   h.bytes = (int32_t)off;
   out->h = h;
   out->blob.assign(off, 0);
@@ -309,6 +414,8 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
   std::memcpy(out->blob.data() + h.region_ofs, rofs.data(), rofs.size() * sizeof(int64_t));
   std::memcpy(out->blob.data() + h.init_qi_ofs, init_qi.data(), init_qi.size());
   std::memcpy(out->blob.data() + h.final_ofs, fin.data(), fin.size() * sizeof(int16_t));
+  std::memcpy(out->blob.data() + h.bu_steps_ofs, bu.data(), bu.size() * sizeof(SiteStep));
+  std::memcpy(out->blob.data() + h.bu_final_ofs, bu_fin.data(), bu_fin.size() * sizeof(int16_t));
   return "";
 }
 

@@ -34,7 +34,7 @@ struct SiteStep {
   uint8_t A, B;    // MPO bond dimension on the left / right of the site (1 or 2)
   uint8_t qi, qo;  // physical dimension before / after the step
   uint8_t act;     // position of the active column inside the site
-  uint8_t pad0;
+  uint8_t tr;      // 1: transposed MPO (bottom-up sweep), codes indexed [a][so][si][b]
   int16_t Dl_old, Dr_old;  // MPS bonds of the input site tensor
   int16_t m;               // Dl_old * A: rows of the site matrix in the right-to-left sweep
   int16_t k;               // rows kept by its LQ factorisation: min(m, qo * kr)
@@ -72,8 +72,13 @@ struct PlanHeader {  // device-visible, followed by the tables at the offsets be
   int32_t region_ofs;   // int64 element offset of each site's scratch region [nsite]
   int32_t init_qi_ofs;  // uint8 physical dimension of each site before step 0 [nsite]
   int32_t final_ofs;    // int16 [nsite][3]: Dl, qo, Dr of the final MPS
+  int32_t bu_steps_ofs; // SiteStep[nstep][nsite]: bottom-up sweep, row nstep-1 first (transposed MPOs)
+  int32_t bu_final_ofs; // int16 [nsite][3]: dims of the bottom-up MPS after its last row
   int32_t bytes;        // total blob size
-  int64_t scratch_elems;  // scratch elements per contraction (site regions)
+  int64_t scratch_elems;  // scratch elements of one MPS (site regions)
+  int64_t mps_elems;      // elements of one truncated MPS (sum over sites of Dl*q*Dr, max over rows)
+  int64_t env_elems;      // elements of the left + right environments of one row (adjoint)
+  int64_t tmp_elems;      // elements of one environment temporary (adjoint)
   // maxima used to carve LDS (elements)
   int32_t max_Aj;   // Dl_old * qi * Dr_old           input site tensor
   int32_t max_T;    // m * (Dr_old * B)               one output slice of the MPO-applied site

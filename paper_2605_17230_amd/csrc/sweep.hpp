@@ -105,6 +105,57 @@ __device__ inline void gemm_lds(int M, int N, int K, const Real* A, int lda, con
   }
 }
 
+// GEMM on the matrix cores: C (MxN) = A (MxK) B (KxN) with A, B read through
+// aload(i, k) / bload(k, j) as floats, rounded to bf16, accumulated in FP32 by
+// v_mfma_f32_16x16x32_bf16 (one 16x16 output tile per wave at a time).  With
+// SPLIT each operand is split into bf16 hi + lo parts and the three leading
+// products hi*hi + hi*lo + lo*hi are accumulated (about 16 mantissa bits).
+// Lane layout of the instruction: A lane l holds row l%16, k = 8(l/16)+i;
+// B lane l holds column l%16, k = 8(l/16)+i; D lane l value i is row
+// 4(l/16)+i, column l%16.
+#ifndef TNMLD_EMU
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+template <bool SPLIT, typename ALoad, typename BLoad, typename Store>
+__device__ inline void gemm_mfma_bf16(int M, int N, int K, ALoad aload, BLoad bload, Store store) {
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
+  const int lr = lane & 15, lk = (lane >> 4) * 8;
+  for (int t = wave; t < tm * tn; t += NT / WAVE) {
+    const int i0 = (t / tn) << 4, j0 = (t % tn) << 4;
+    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+    const int r = i0 + lr, c = j0 + lr;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      bf16x8_t ah, bh, al, bl;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int kk = k0 + lk + i;
+        const float a = (r < M && kk < K) ? aload(r, kk) : 0.f;
+        const float b = (kk < K && c < N) ? bload(kk, c) : 0.f;
+        ah[i] = (__bf16)a;
+        bh[i] = (__bf16)b;
+        if (SPLIT) {
+          al[i] = (__bf16)(a - (float)ah[i]);
+          bl[i] = (__bf16)(b - (float)bh[i]);
+        }
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+      if (SPLIT) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rr = i0 + (lane >> 4) * 4 + i;
+      if (rr < M && c < N) store(rr, c, acc[i]);
+    }
+  }
+}
+
+#endif  // TNMLD_EMU
+
 // Householder LQ of X (m x n, row-major, leading dimension ld), in place:
 // X = L Q with L lower-trapezoidal (m x k) and Q (k x n) with orthonormal rows,
 // k = min(m, n).  Reflectors follow the LAPACK convention H = I - tau v v^T

@@ -25,13 +25,19 @@
 #include <vector>
 
 #include "../../include/tnmld.h"
+#include "adjoint.hpp"
 #include "contract.hpp"
 #include "plan.hpp"
 #include "sweep.hpp"
 
+// GEMM mode of the bf16 precision form (split bf16x3 keeps ~16 mantissa bits)
+#ifndef BF16_GEMM_MODE
+#define BF16_GEMM_MODE GEMM_BF16X3
+#endif
+
 namespace tnmld {
 
-template <typename Real, typename Fac>
+template <typename Real, typename Fac, int GM>
 __global__ __launch_bounds__(NT) void fwd_kernel(JobTable jt, unsigned long long* counter, char* scratch,
                                                   int64_t scratch_stride, LdsLayout lay) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -50,10 +56,43 @@ __global__ __launch_bounds__(NT) void fwd_kernel(JobTable jt, unsigned long long
     const int64_t b = local >> 2;
     const int mlog = (int)(local & 3);
     int label = 0;
-    const double lz = contract_one<Real, Fac>(job, b, mlog, smem, lay, scr, &label);
+    const double lz = contract_one<Real, Fac, GM>(job, b, mlog, smem, lay, scr, &label);
     if (threadIdx.x == 0) job.logz[b * 4 + label] = lz;
     __syncthreads();
   }
+}
+
+// Backward: each work-group walks a fixed stride of items (deterministic order)
+// and accumulates into its own FP64 partial gradient.
+template <typename Real, typename Fac, int GM>
+__global__ __launch_bounds__(NT) void bwd_kernel(JobTable jt, char* scratch, int64_t scratch_stride, LdsLayout lay,
+                                                  int kseg, double* partials, int64_t part_stride) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  Real* scr = reinterpret_cast<Real*>(scratch + (int64_t)blockIdx.x * scratch_stride);
+  double* mypart = partials + (int64_t)blockIdx.x * part_stride;
+  for (int64_t item = blockIdx.x; item < jt.nitems; item += gridDim.x) {
+    int jb = 0;
+    while (jb + 1 < jt.n && jt.j[jb + 1].item_begin <= item) ++jb;
+    const JobDev& job = jt.j[jb];
+    const int64_t local = item - job.item_begin;
+    adjoint_one<Real, Fac, GM>(job, local >> 2, (int)(local & 3), smem, lay, scr, kseg, mypart + job.part_ofs);
+    __syncthreads();
+  }
+}
+
+__global__ void fill_zero_f64(double* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// out[i] += sum over work-groups w (in order) of partials[w * stride + ofs + i]
+__global__ void reduce_partials(const double* partials, int64_t stride, int nwg, int64_t ofs, int64_t len,
+                                double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  double acc = 0.0;
+  for (int w = 0; w < nwg; ++w) acc += partials[(int64_t)w * stride + ofs + i];
+  out[i] += acc;
 }
 
 __global__ void zero_counter(unsigned long long* c) {
@@ -126,9 +165,9 @@ int device_info(DevInfo* out) {
 
 // element sizes of the MPS storage / GEMM type and of the factorisation type
 int real_bytes(int precision) { return precision == TN_FP64 ? 8 : 4; }
-int fac_bytes(int precision) { return precision == TN_FP32_PLAIN ? 4 : 8; }
+int fac_bytes(int precision) { return (precision == TN_FP32_PLAIN || precision == TN_BF16) ? 4 : 8; }
 bool precision_built(int precision) {
-  return precision == TN_FP64 || precision == TN_FP32 || precision == TN_FP32_PLAIN;
+  return precision >= TN_FP64 && precision <= TN_FP32_PLAIN;
 }
 
 // largest usable LDS per block on gfx950 when no device is queried
@@ -299,10 +338,10 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
   return TN_OK;
 }
 
-template <typename Real, typename Fac>
+template <typename Real, typename Fac, int GM>
 int launch_fwd(const Launch& L, int nwg, char* ws_scratch, unsigned long long* counter, hipStream_t st) {
   LdsLayout lay = lds_layout(L.merged, sizeof(Real), sizeof(Fac));
-  auto kern = fwd_kernel<Real, Fac>;
+  auto kern = fwd_kernel<Real, Fac, GM>;
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                           lay.bytes) != hipSuccess)
     return fail(TN_EDEVICE, "hipFuncSetAttribute failed");
@@ -332,12 +371,94 @@ int run_forward(const tn_segment* segs, int32_t nseg, void* workspace, size_t ws
     unsigned long long* counter = reinterpret_cast<unsigned long long*>(base) + li;
     char* scr = base + off;
     off += (size_t)L.nwg * align_up((size_t)L.scratch_elems * real_bytes(L.precision));
-    if (L.precision == TN_FP64) rc = launch_fwd<double, double>(L, L.nwg, scr, counter, st);
-    else if (L.precision == TN_FP32) rc = launch_fwd<float, double>(L, L.nwg, scr, counter, st);
-    else rc = launch_fwd<float, float>(L, L.nwg, scr, counter, st);
+    if (L.precision == TN_FP64) rc = launch_fwd<double, double, GEMM_VALU>(L, L.nwg, scr, counter, st);
+    else if (L.precision == TN_FP32) rc = launch_fwd<float, double, GEMM_VALU>(L, L.nwg, scr, counter, st);
+    else if (L.precision == TN_BF16) rc = launch_fwd<float, float, BF16_GEMM_MODE>(L, L.nwg, scr, counter, st);
+    else rc = launch_fwd<float, float, GEMM_VALU>(L, L.nwg, scr, counter, st);
     if (rc) return rc;
     ++li;
   }
+  return TN_OK;
+}
+
+// Layout of the backward call: one launch (all segments share a precision).
+struct BwdLayout {
+  int precision = 0;
+  JobTable jt{};
+  int seg_of_job[TN_MAX_SEGMENTS] = {};
+  PlanHeader merged{};
+  int nwg = 0, kseg = 1;
+  int64_t scratch_stride = 0, part_stride = 0;
+  size_t fwd_bytes = 0, total = 0;
+};
+
+int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
+  std::vector<Launch> launches;
+  size_t fwd = 0;
+  int nwgf = 0;
+  DevInfo di;
+  int rc = validate(segs, nseg);
+  if (rc) return rc;
+  if ((rc = device_info(&di))) return rc;
+  if ((rc = plan_launches(segs, nseg, std::min(di.lds_max, kLdsLimit), &launches, &fwd, &nwgf))) return rc;
+  if (launches.size() > 1) return fail(TN_EUNSUPPORTED, "backward segments must share one precision");
+  bl->fwd_bytes = align_up(fwd);
+  if (launches.empty()) {
+    bl->total = bl->fwd_bytes;
+    return TN_OK;
+  }
+  const Launch& L = launches[0];
+  bl->precision = L.precision;
+  bl->jt = L.jt;
+  bl->merged = L.merged;
+  // map jobs back to segments (same order as plan_launches: by decreasing d, stable)
+  std::vector<int> order(nseg);
+  for (int i = 0; i < nseg; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return segs[a].d > segs[b].d; });
+  int ji = 0;
+  int64_t part = 0, per_item = 0;
+  int nstep_max = 1;
+  for (int oi : order) {
+    if (segs[oi].count == 0) continue;
+    bl->seg_of_job[ji] = oi;
+    JobDev& j = bl->jt.j[ji];
+    j.logp = segs[oi].out_logp;
+    j.part_ofs = part;
+    part += (int64_t)segs[oi].n_models * segs[oi].d * segs[oi].d * 3;
+    const PlanHeader* H = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      for (auto& kv : g_plans)
+        if (kv.second->dev == j.plan) H = &kv.second->plan.h;
+    }
+    if (!H) return fail(TN_EDEVICE, "internal: plan not cached");
+    const int ks = (int)std::ceil(std::sqrt((double)H->nstep));
+    const int ncp = (H->nstep + ks - 1) / ks;
+    nstep_max = std::max(nstep_max, H->nstep);
+    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems + (int64_t)(ncp + ks) * H->mps_elems + H->env_elems +
+                                               3 * H->tmp_elems);
+    ++ji;
+  }
+  bl->kseg = (int)std::ceil(std::sqrt((double)nstep_max));
+  // recompute the per-item scratch with the common segment length
+  per_item = 0;
+  for (int i = 0; i < ji; ++i) {
+    const PlanHeader* H = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      for (auto& kv : g_plans)
+        if (kv.second->dev == bl->jt.j[i].plan) H = &kv.second->plan.h;
+    }
+    const int ncp = (H->nstep + bl->kseg - 1) / bl->kseg;
+    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems + (int64_t)(ncp + bl->kseg) * H->mps_elems +
+                                               H->env_elems + 3 * H->tmp_elems);
+  }
+  const int lb = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision)).bytes;
+  bl->nwg = std::max(1, wgs_for(lb)) * di.cus;
+  bl->scratch_stride = (int64_t)align_up((size_t)per_item * real_bytes(L.precision));
+  bl->part_stride = (part + 31) / 32 * 32;
+  bl->total = bl->fwd_bytes + align_up((size_t)bl->nwg * bl->part_stride * sizeof(double)) +
+              (size_t)bl->nwg * bl->scratch_stride;
   return TN_OK;
 }
 
@@ -349,7 +470,11 @@ using namespace tnmld;
 extern "C" {
 
 size_t tn_workspace_size(const tn_segment* segs, int32_t nseg, int32_t with_backward) {
-  (void)with_backward;
+  if (with_backward) {
+    BwdLayout bl;
+    if (plan_backward(segs, nseg, &bl)) return 0;
+    return bl.total;
+  }
   std::vector<Launch> launches;
   size_t need = 0;
   int nwg = 0;
@@ -388,14 +513,45 @@ int tn_decode_batch(const tn_segment* segs, int32_t nseg, double tie_tol, void* 
 
 int tn_coset_loglik_backward(const tn_segment* segs, int32_t nseg, const double* const* grad_logp,
                              double* const* grad_log_rates, void* workspace, size_t ws_bytes, void* stream) {
-  (void)segs;
-  (void)nseg;
-  (void)grad_logp;
-  (void)grad_log_rates;
-  (void)workspace;
-  (void)ws_bytes;
-  (void)stream;
-  return fail(TN_EUNSUPPORTED, "backward not built yet");
+  BwdLayout bl;
+  int rc = plan_backward(segs, nseg, &bl);
+  if (rc) return rc;
+  if (!grad_logp || !grad_log_rates) return fail(TN_EINVAL, "null gradient arrays");
+  for (int i = 0; i < nseg; ++i) {
+    if (segs[i].count > 0 && (!grad_logp[i] || !grad_log_rates[i] || !segs[i].out_logp))
+      return fail(TN_EINVAL, "backward needs grad_logp, grad_log_rates and out_logp for every segment");
+  }
+  if (!workspace || ws_bytes < bl.total) return fail(TN_EINVAL, "workspace too small: need " + std::to_string(bl.total));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // forward pass: log Z and log P(s) (the coset weights of the backward)
+  if ((rc = tn_coset_loglik(segs, nseg, workspace, ws_bytes, stream))) return rc;
+  char* base = reinterpret_cast<char*>(workspace) + bl.fwd_bytes;
+  double* partials = reinterpret_cast<double*>(base);
+  char* scratch = base + align_up((size_t)bl.nwg * bl.part_stride * sizeof(double));
+  fill_zero_f64<<<256, 256, 0, st>>>(partials, (int64_t)bl.nwg * bl.part_stride);
+  JobTable jt = bl.jt;
+  for (int i = 0; i < jt.n; ++i) jt.j[i].gradp = grad_logp[bl.seg_of_job[i]];
+  LdsLayout lay = lds_layout(bl.merged, real_bytes(bl.precision), fac_bytes(bl.precision));
+  const void* kern = nullptr;
+  if (bl.precision == TN_FP64) kern = reinterpret_cast<const void*>(bwd_kernel<double, double, GEMM_VALU>);
+  else if (bl.precision == TN_FP32) kern = reinterpret_cast<const void*>(bwd_kernel<float, double, GEMM_VALU>);
+  else if (bl.precision == TN_BF16) kern = reinterpret_cast<const void*>(bwd_kernel<float, float, BF16_GEMM_MODE>);
+  else kern = reinterpret_cast<const void*>(bwd_kernel<float, float, GEMM_VALU>);
+  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, lay.bytes) != hipSuccess)
+    return fail(TN_EDEVICE, "hipFuncSetAttribute failed");
+  int kseg = bl.kseg;
+  int64_t sstride = bl.scratch_stride, pstride = bl.part_stride;
+  void* args[] = {&jt, &scratch, &sstride, &lay, &kseg, &partials, &pstride};
+  if (hipLaunchKernel(kern, dim3(bl.nwg), dim3(NT), args, lay.bytes, st) != hipSuccess)
+    return fail(TN_EDEVICE, "backward launch failed");
+  for (int i = 0; i < jt.n; ++i) {
+    const tn_segment& sg = segs[bl.seg_of_job[i]];
+    const int64_t len = (int64_t)sg.n_models * sg.d * sg.d * 3;
+    reduce_partials<<<(unsigned)((len + 255) / 256), 256, 0, st>>>(partials, pstride, bl.nwg, jt.j[i].part_ofs, len,
+                                                                   grad_log_rates[bl.seg_of_job[i]]);
+  }
+  if (hipGetLastError() != hipSuccess) return fail(TN_EDEVICE, "reduction launch failed");
+  return TN_OK;
 }
 
 int tn_code_stabilizers(int32_t d, int32_t* type_out, int32_t* support_out) {

@@ -1,0 +1,197 @@
+"""Adjoint of the boundary-MPS contraction on the GPU: d sum_b g_b log P(s_b) /
+d ln p_{q,P}, against the FP64 oracle (posterior marginals, O5), against
+central finite differences of the exact oracle and of the GPU forward, and
+against the score identity of a correctly specified model."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _tn():
+    import paper_2605_17230_amd as tn
+    return tn
+
+
+def _seg(d, chi, syn, rates, prec, mi=None):
+    tn = _tn()
+    return tn.SegmentInput(d, chi, torch.from_numpy(np.ascontiguousarray(syn)).to(DEV),
+                           torch.from_numpy(np.ascontiguousarray(rates)).to(DEV),
+                           None if mi is None else torch.from_numpy(mi.astype(np.int32)).to(DEV), prec)
+
+
+def gpu_grad(d, chi, syn, rates, prec, gw, mi=None):
+    tn = _tn()
+    outs, grads = tn.coset_loglik_backward([_seg(d, chi, syn, rates, prec, mi)],
+                                           [torch.from_numpy(np.asarray(gw, np.float64)).to(DEV)])
+    g = grads[0].cpu().numpy()
+    return (g[0] if np.ndim(rates) == 2 else g), outs[0].logz.cpu().numpy(), outs[0].logp.cpu().numpy()
+
+
+def oracle_grad(d, rates, syn, gw):
+    g = np.zeros((d * d, 3))
+    for s, w in zip(syn, gw):
+        g += w * oracle.grad_logp(d, rates, s)[0]
+    return g
+
+
+def oracle_fd(d, rates, syn, gw, coords, h=1e-5):
+    """Central differences of sum_b g_b log P(s_b) in theta = ln p (exact O3)."""
+    out = []
+    for q, k in coords:
+        vals = []
+        for sgn in (1, -1):
+            r = rates.copy()
+            r[q, k] *= np.exp(sgn * h)
+            lz = oracle.transfer(d, r, syn)
+            vals.append(float(np.dot(gw, np.logaddexp.reduce(lz, 1))))
+        out.append((vals[0] - vals[1]) / (2 * h))
+    return np.array(out)
+
+
+def gpu_fd(d, chi, syn, rates, prec, gw, coords, h=1e-4):
+    tn = _tn()
+    s = torch.from_numpy(np.ascontiguousarray(syn)).to(DEV)
+    out = []
+    for q, k in coords:
+        vals = []
+        for sgn in (1, -1):
+            r = rates.copy()
+            r[q, k] *= np.exp(sgn * h)
+            _, lp, _ = tn.decode(s, torch.from_numpy(r).to(DEV), d, chi, prec)
+            vals.append(float(np.dot(gw, lp.cpu().numpy())))
+        out.append((vals[0] - vals[1]) / (2 * h))
+    return np.array(out)
+
+
+def rel_err(got, ref):
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+@pytest.mark.parametrize("d,chi", [(3, 0), (3, 4), (5, 0)])
+def test_grad_exact_fp64(d, chi):
+    rates = synth.inhomogeneous(d, 0.01, 0.15, seed=11 + d)
+    smp = synth.sample(d, rates, 6, seed=21 + d)
+    gw = np.random.default_rng(d).normal(size=6)
+    got, _, _ = gpu_grad(d, chi, smp["syndromes"], rates, "fp64", gw)
+    ref = oracle_grad(d, rates, smp["syndromes"], gw)
+    assert rel_err(got, ref) < 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("fp32plain", 1e-3), ("bf16", 2e-2)])
+def test_grad_exact_reduced_precision(prec, tol):
+    d = 5
+    rates = synth.inhomogeneous(d, 0.01, 0.15, seed=3)
+    smp = synth.sample(d, rates, 6, seed=4)
+    gw = np.ones(6)
+    got, _, _ = gpu_grad(d, 0, smp["syndromes"], rates, prec, gw)
+    ref = oracle_grad(d, rates, smp["syndromes"], gw)
+    assert rel_err(got, ref) < tol
+
+
+def test_grad_models_and_index():
+    """Two noise models selected per syndrome: each model's gradient only
+    collects the syndromes that use it."""
+    d = 5
+    rates = np.stack([synth.depolarizing(d, 0.08), synth.biased(d, 0.1, 10.0)])
+    smp = synth.sample(d, rates[0], 8, seed=9)
+    mi = np.array([0, 1] * 4)
+    gw = np.linspace(0.5, 1.5, 8)
+    got, _, _ = gpu_grad(d, 0, smp["syndromes"], rates, "fp64", gw, mi)
+    for m in range(2):
+        sel = mi == m
+        ref = oracle_grad(d, rates[m], smp["syndromes"][sel], gw[sel])
+        assert rel_err(got[m], ref) < 1e-10
+
+
+def test_grad_truncated_d9_vs_oracle():
+    d, chi = 9, 16
+    rates = synth.inhomogeneous(d, 0.02, 0.12, seed=5)
+    smp = synth.sample(d, rates, 2, seed=6)
+    gw = np.array([1.0, -0.5])
+    got, _, _ = gpu_grad(d, chi, smp["syndromes"], rates, "fp64", gw)
+    ref = oracle_grad(d, rates, smp["syndromes"], gw)
+    assert rel_err(got, ref) < 1e-4
+
+
+def test_grad_d11_chi24_central_differences():
+    """Adjoint vs central differences of the GPU forward and of the exact
+    oracle on sampled coordinates (d = 11, chi = 24, FP64)."""
+    d, chi = 11, 24
+    rates = synth.depolarizing(d, 0.1)
+    smp = synth.sample(d, rates, 4, seed=12)
+    gw = np.ones(4)
+    got, _, _ = gpu_grad(d, chi, smp["syndromes"], rates, "fp64", gw)
+    rng = np.random.default_rng(0)
+    coords = [(int(q), int(k)) for q, k in zip(rng.integers(0, d * d, 6), rng.integers(0, 3, 6))]
+    sel = np.array([got[q, k] for q, k in coords])
+    fd_gpu = gpu_fd(d, chi, smp["syndromes"], rates, "fp64", gw, coords)
+    fd_orc = oracle_fd(d, rates, smp["syndromes"], gw, coords)
+    scale = np.max(np.abs(got))
+    assert np.max(np.abs(sel - fd_gpu)) < 1e-4 * scale
+    assert np.max(np.abs(sel - fd_orc)) < 1e-4 * scale
+
+
+def test_grad_full_size_d17_chi32_central_differences():
+    """The benchmark's configuration (d = 17, chi = 32, depolarizing 0.12) on a
+    sample of syndromes: adjoint vs central differences of the forward."""
+    d, chi = 17, 32
+    rates = synth.depolarizing(d, 0.12)
+    smp = synth.sample(d, rates, 8, seed=3000)
+    gw = np.ones(8)
+    got, _, _ = gpu_grad(d, chi, smp["syndromes"], rates, "fp64", gw)
+    coords = [(0, 0), (144, 1), (288, 2), (100, 2)]
+    sel = np.array([got[q, k] for q, k in coords])
+    fd = gpu_fd(d, chi, smp["syndromes"], rates, "fp64", gw, coords)
+    assert np.max(np.abs(sel - fd)) < 1e-4 * np.max(np.abs(got))
+
+
+def test_grad_deterministic_and_zero_weights():
+    d, chi = 7, 8
+    rates = synth.depolarizing(d, 0.1)
+    smp = synth.sample(d, rates, 40, seed=2)
+    gw = np.random.default_rng(1).normal(size=40)
+    a, _, _ = gpu_grad(d, chi, smp["syndromes"], rates, "fp32", gw)
+    b, _, _ = gpu_grad(d, chi, smp["syndromes"], rates, "fp32", gw)
+    assert np.array_equal(a, b)
+    z, _, _ = gpu_grad(d, chi, smp["syndromes"], rates, "fp32", np.zeros(40))
+    assert not np.any(z)
+
+
+def test_autograd_function():
+    tn = _tn()
+    d = 5
+    rates = synth.inhomogeneous(d, 0.02, 0.1, seed=8)
+    smp = synth.sample(d, rates, 5, seed=8)
+    theta = torch.from_numpy(np.log(rates)).to(DEV).requires_grad_(True)
+    syn = torch.from_numpy(smp["syndromes"]).to(DEV)
+    logp, logz = tn.log_posterior(theta, syn, d, 0, "fp64")
+    w = torch.arange(1, 6, dtype=torch.float64, device=DEV)
+    (w * logp).sum().backward()
+    ref = oracle_grad(d, rates, smp["syndromes"], np.arange(1, 6))
+    assert rel_err(theta.grad.cpu().numpy(), ref) < 1e-10
+    lz_ref = oracle.transfer(d, rates, smp["syndromes"])
+    assert np.max(np.abs(logz.cpu().numpy() - lz_ref)) < 1e-9
+
+
+def test_score_identity():
+    """Under the model that generated the syndromes, E_s[grad log P(s)] = 0:
+    the summed score over a large sample stays within sampling error."""
+    d, chi = 7, 16
+    rates = synth.depolarizing(d, 0.1)
+    nb, per = 16, 256
+    smp = synth.sample(d, rates, nb * per, seed=77)
+    tot = []
+    for i in range(nb):
+        syn = smp["syndromes"][i * per:(i + 1) * per]
+        g, _, _ = gpu_grad(d, chi, syn, rates, "fp64", np.ones(per))
+        tot.append(g.sum(axis=0))  # per Pauli, summed over qubits
+    tot = np.array(tot)
+    mean, sd = tot.mean(0), tot.std(0, ddof=1)
+    assert np.all(np.abs(mean) < 5 * sd / np.sqrt(nb) + 1e-9)

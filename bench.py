@@ -34,7 +34,20 @@ def parse():
     ap.add_argument("--count", type=int, default=COUNT)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (reference kernel for HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy of known size: 1 GiB read + 1 GiB written, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of the decoding kernel."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}), flush=True)
 
 
 def cpu_baseline(syn, rates, target_s):
@@ -60,8 +73,11 @@ def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(syndromes shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+              "(syndromes would shard across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
+    if a.copy_calibration:
+        copy_calibration()
+        return
     import torch
 
     import paper_2605_17230_amd as tn

@@ -298,7 +298,7 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
         // M = (Qf^T W) S U'^T; keep the Dn largest singular values
         for (int e = tid; e < k2 * k2; e += NT) Vv[(e / k2) * ldl + (e % k2)] = (e / k2 == e % k2) ? Fac(1) : Fac(0);
         __syncthreads();
-        jacobi_svd<Fac>(Lt, kr, k2, ldl, Vv, ldl, SplitTol<Fac>::v, w.s_flag);
+        jacobi_svd<Fac>(Lt, kr, k2, ldl, Vv, ldl, SplitTol<Fac>::v, w.s_flag, dred);
         for (int c = tid; c < k2; c += NT) {
           double s2 = 0;
           for (int r = 0; r < kr; ++r) s2 += (double)Lt[c * ldl + r] * (double)Lt[c * ldl + r];

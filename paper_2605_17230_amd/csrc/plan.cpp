@@ -342,6 +342,8 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
   h.tmp_elems = (tmp_max + 63) / 64 * 64;
   h.mps_elems = (mps_max + 63) / 64 * 64;
   h.env_elems = (2 * env_max + 63) / 64 * 64;
+  // the truncation SVD keeps a column pair of up to 128 rows in registers
+  if (h.max_kr > 128) return "bond dimension above 128 before truncation: lower chi";
 
 
   // final MPS shape per site

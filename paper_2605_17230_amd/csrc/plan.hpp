@@ -141,7 +141,7 @@ inline LdsLayout lds_layout(const PlanHeader& h, int rb, int fb) {
   const int32_t nv = h.max_n > h.max_rows ? h.max_n : h.max_rows;
   o.tau = p; p += pad64b((int64_t)nh * fb);
   o.diag = p; p += pad64b((int64_t)nh * fb);
-  o.v = p; p += pad64b((int64_t)nv * fb);
+  o.v = p; p += pad64b((int64_t)2 * nv * fb);
   o.W = p; p += pad64b(64 * rb);
   o.red = p; p += 64 * 8;
   o.perm = p; p += pad64b((int64_t)h.max_kr * 4);

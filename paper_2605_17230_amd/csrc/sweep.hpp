@@ -1,6 +1,6 @@
 // Device building blocks of the boundary-MPS sweep (gfx950, wave64).
 //
-// One work-group of NT = 256 threads contracts one (syndrome, coset) pair at a
+// One work-group of NT = 512 threads contracts one (syndrome, coset) pair at a
 // time.  Every dense matrix of a site step lives in LDS; the MPS itself lives
 // in a per-work-group scratch region of HBM (it does not fit in LDS at
 // chi = 32: 33 sites x 8-64 KB).  Routines here are work-group collective:
@@ -53,10 +53,41 @@ struct TinyNorm<float> {
   static constexpr double v = 1e-30;
 };
 
-// sum over aligned groups of G consecutive lanes (G a power of two <= 64)
+#ifndef TNMLD_EMU
+// Lane moves inside a row of 16 lanes by DPP (a VALU operand modifier: no LDS
+// traffic).  Controls: 0xB1 quad_perm [1,0,3,2], 0x4E quad_perm [2,3,0,1],
+// 0x141 row_half_mirror (lane i <- 7-i in each half-row), 0x140 row_mirror
+// (lane i <- 15-i).  Every lane of the row must be active.
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+#endif
+
+// Sum over aligned groups of G consecutive lanes (G a power of two <= 64),
+// returned to every lane of the group.  Partners add in commutative pairs, so
+// every lane of a group holds the bitwise-identical sum.  G <= 16 stays inside
+// a DPP row: groups may then diverge from each other; G >= 32 needs the whole
+// wave active.
 template <typename Real>
 __device__ inline Real group_sum(Real v, int G) {
-  for (int off = G >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+#ifdef TNMLD_EMU
+  for (int off = G >> 1; off > 0; off >>= 1) v += emu_shfl_xor(v, off, G);
+#else
+  if (G >= 2) v += dpp_move<0xB1>(v);
+  if (G >= 4) v += dpp_move<0x4E>(v);
+  if (G >= 8) v += dpp_move<0x141>(v);
+  if (G >= 16) v += dpp_move<0x140>(v);
+  if (G >= 32) v += __shfl_xor(v, 16, WAVE);
+  if (G >= 64) v += __shfl_xor(v, 32, WAVE);
+#endif
   return v;
 }
 
@@ -164,82 +195,117 @@ __device__ inline void gemm_mfma_bf16(int M, int N, int K, ALoad aload, BLoad bl
 // Norms and dot products accumulate in FP64 so that FP32 squares of small
 // entries cannot underflow.  On return row i holds v_i in columns i+1..n-1,
 // the strictly lower part holds L, diag[i] = L[i][i], tau[i] = tau_i.
+//
+// One barrier per reflector: lane group 0 (16 lanes) owns the next row.  It
+// updates that row, takes its tail norm and builds the next reflector while
+// the other groups are still applying the current one to the rows below; the
+// FP64 tau of step i is handed over in red[i & 1].
 template <typename Real>
 __device__ void lq_factor(Real* X, int m, int n, int ld, Real* tau, Real* diag, double* red) {
   const int k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
+  constexpr int NG = NT / 16;
+  double tail2 = 0.0;  // group 0: squared norm of row i beyond column i
+  if (grp == 0 && k > 0) {
+    for (int c = 1 + lane; c < n; c += 16) tail2 += (double)X[c] * (double)X[c];
+    tail2 = group_sum(tail2, 16);
+  }
   for (int i = 0; i < k; ++i) {
     Real* xi = X + i * ld;
-    double part = 0;
-    for (int c = i + 1 + tid; c < n; c += NT) part += (double)xi[c] * (double)xi[c];
-    const double tail2 = block_sum(part, red);
-    const double x0 = (double)xi[i];
-    const double nrm = sqrt(tail2 + x0 * x0);
-    // reflector; rows at the bottom of the real range are treated as exact zeros
-    const bool live = tail2 > 0.0 && nrm > TinyNorm<Real>::v;
-    double beta = x0, t = 0.0, scale = 0.0;
-    if (live) {
-      beta = x0 >= 0.0 ? -nrm : nrm;
-      t = (beta - x0) / beta;
-      scale = 1.0 / (x0 - beta);
-    }
-    __syncthreads();
-    if (live)
-      for (int c = i + 1 + tid; c < n; c += NT) xi[c] = Real((double)xi[c] * scale);
-    if (tid == 0) {
-      tau[i] = Real(t);
-      diag[i] = Real(beta);
-    }
-    __syncthreads();
-    if (live) {
-      for (int r0 = i + 1; r0 < m; r0 += NT / 16) {
-        const int r = r0 + grp;
-        const bool act = r < m;
-        Real* xr = X + (act ? r : 0) * ld;
-        double dot = 0;
-        const double xri = act ? (double)xr[i] : 0.0;  // read before lane 0 rewrites it
-        if (act)
-          for (int c = i + 1 + lane; c < n; c += 16) dot += (double)xr[c] * (double)xi[c];
-        dot = group_sum(dot, 16);  // wave-uniform trip count: every lane shuffles
-        if (act) {
-          const Real w = Real((dot + xri) * t);
-          if (lane == 0) xr[i] -= w;
-          for (int c = i + 1 + lane; c < n; c += 16) xr[c] -= w * xi[c];
-        }
+    if (grp == 0) {
+      const double x0 = (double)xi[i];
+      const double nrm = sqrt(tail2 + x0 * x0);
+      // reflector; rows at the bottom of the real range are treated as exact zeros
+      const bool live = tail2 > 0.0 && nrm > TinyNorm<Real>::v;
+      double beta = x0, t = 0.0;
+      if (live) {
+        beta = x0 >= 0.0 ? -nrm : nrm;
+        t = (beta - x0) / beta;
+        const double scale = 1.0 / (x0 - beta);
+        for (int c = i + 1 + lane; c < n; c += 16) xi[c] = Real((double)xi[c] * scale);
+      }
+      if (lane == 0) {
+        tau[i] = Real(t);
+        diag[i] = Real(beta);
+        red[i & 1] = t;
       }
     }
     __syncthreads();
+    const double t = red[i & 1];
+    if (grp == 0) {
+      const int r = i + 1;
+      if (r < m) {
+        Real* xr = X + r * ld;
+        double nt2 = 0.0;
+        if (t != 0.0) {
+          const double xri = (double)xr[i];  // read before lane 0 rewrites it
+          double dot = 0.0;
+          for (int c = i + 1 + lane; c < n; c += 16) dot += (double)xr[c] * (double)xi[c];
+          dot = group_sum(dot, 16);
+          const Real w = Real((dot + xri) * t);
+          if (lane == 0) xr[i] -= w;
+          for (int c = i + 1 + lane; c < n; c += 16) {
+            const Real y = xr[c] - w * xi[c];
+            xr[c] = y;
+            if (c > r) nt2 += (double)y * (double)y;
+          }
+        } else {
+          for (int c = r + 1 + lane; c < n; c += 16) nt2 += (double)xr[c] * (double)xr[c];
+        }
+        tail2 = group_sum(nt2, 16);
+      }
+    } else if (t != 0.0) {
+      for (int r = i + 1 + grp; r < m; r += NG - 1) {
+        Real* xr = X + r * ld;
+        const double xri = (double)xr[i];
+        double dot = 0.0;
+        for (int c = i + 1 + lane; c < n; c += 16) dot += (double)xr[c] * (double)xi[c];
+        dot = group_sum(dot, 16);
+        const Real w = Real((dot + xri) * t);
+        if (lane == 0) xr[i] -= w;
+        for (int c = i + 1 + lane; c < n; c += 16) xr[c] -= w * xi[c];
+      }
+    }
+    // no barrier: the next reflector touches only row i + 1, which group 0 owns
   }
+  __syncthreads();
 }
 
 // After lq_factor and after L has been copied out: overwrite rows 0..k-1 of X
-// with the explicit Q = [I_k 0] H_{k-1} ... H_0.  v is scratch of length n.
+// with the explicit Q = [I_k 0] H_{k-1} ... H_0.  v is scratch of length 2n
+// (the reflector of step i is staged in v + (i & 1) * n one step ahead, so a
+// step needs a single barrier).
 template <typename Real>
 __device__ void lq_form_q(Real* X, int m, int n, int ld, const Real* tau, Real* v) {
   const int k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
+  if (k == 0) return;
+  {
+    Real* vb = v + ((k - 1) & 1) * n;
+    const Real* xi = X + (k - 1) * ld;
+    for (int c = tid; c < n; c += NT) vb[c] = c < k - 1 ? Real(0) : (c == k - 1 ? Real(1) : xi[c]);
+  }
+  __syncthreads();
   for (int i = k - 1; i >= 0; --i) {
-    Real* xi = X + i * ld;
-    for (int c = i + 1 + tid; c < n; c += NT) v[c] = xi[c];
-    if (tid == 0) v[i] = Real(1);
-    __syncthreads();
+    const Real* vb = v + (i & 1) * n;
     const Real t = tau[i];
     if (t != Real(0)) {
-      for (int r0 = i + 1; r0 < k; r0 += NT / 16) {
-        const int r = r0 + grp;
-        const bool act = r < k;
-        Real* xr = X + (act ? r : 0) * ld;
+      for (int r = i + 1 + grp; r < k; r += NT / 16) {
+        Real* xr = X + r * ld;
         double dot = 0;
-        if (act)
-          for (int c = i + lane; c < n; c += 16) dot += (double)xr[c] * (double)v[c];
+        for (int c = i + lane; c < n; c += 16) dot += (double)xr[c] * (double)vb[c];
         dot = group_sum(dot, 16);
-        if (act) {
-          const Real w = Real(dot) * t;
-          for (int c = i + lane; c < n; c += 16) xr[c] -= w * v[c];
-        }
+        const Real w = Real(dot) * t;
+        for (int c = i + lane; c < n; c += 16) xr[c] -= w * vb[c];
       }
     }
-    for (int c = tid; c < n; c += NT) xi[c] = c < i ? Real(0) : ((c == i ? Real(1) : Real(0)) - t * v[c]);
+    Real* xi = X + i * ld;
+    for (int c = tid; c < n; c += NT) xi[c] = c < i ? Real(0) : ((c == i ? Real(1) : Real(0)) - t * vb[c]);
+    if (i > 0) {
+      Real* vn = v + ((i - 1) & 1) * n;
+      const Real* xp = X + (i - 1) * ld;
+      for (int c = tid; c < n; c += NT) vn[c] = c < i - 1 ? Real(0) : (c == i - 1 ? Real(1) : xp[c]);
+    }
     __syncthreads();
   }
 }
@@ -247,18 +313,37 @@ __device__ void lq_form_q(Real* X, int m, int n, int ld, const Real* tau, Real* 
 // One-sided (Hestenes) Jacobi on the columns of M (rows x cols, column-major,
 // leading dimension ldm), accumulating the rotations in V (cols x cols,
 // column-major, ldv), which must hold the identity on entry.  Afterwards the
-// columns of M are mutually orthogonal to a relative cosine below tol:
-// M_in V = M_out, and the column norms are the singular values.  Parallel cyclic ordering (circle method): each
-// round rotates cols'/2 disjoint pairs, one pair per group of G lanes.
+// columns of M are mutually orthogonal: M_in V = M_out, and the column norms
+// are the singular values.  Parallel cyclic ordering (circle method): each
+// round rotates cols'/2 disjoint pairs, one pair per group of G lanes, with
+// the pair's columns held in registers.
+//
+// A pair is left alone once its cosine is below tol, or once what a rotation
+// would remove is below the rounding level of the storage type: |a.b| <=
+// k eps max(|a|^2, |b|^2) (the component of the smaller column along the
+// larger one is noise of the larger), or |a.b| <= (k eps |M|_F)^2 (both
+// columns are noise of the matrix), with k = sqrt(rows).  Without the last
+// two tests, columns at the rounding floor of a strongly graded matrix keep
+// rotating forever.  Returns the number of sweeps.
 template <typename Real>
-__device__ void jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv, double tol, int* flag) {
-  if (cols < 2) return;
+__device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv, double tol, int* flag,
+                          double* red) {
+  if (cols < 2) return 0;
   const int N = cols + (cols & 1);
   const int P = N >> 1;
   int G = WAVE;
   while (G > 1 && G * P > NT) G >>= 1;
   const int tid = threadIdx.x, g = tid / G, lane = tid % G;
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  double part = 0;
+  for (int c = 0; c < cols; ++c)
+    for (int r = tid; r < rows; r += NT) part += (double)M[c * ldm + r] * (double)M[c * ldm + r];
+  const double nf2 = block_sum(part, red);
+  const double keps = sqrt((double)rows) * (double)Eps<Real>::v;
+  const double floor2 = keps * keps * nf2;
+  constexpr int MAXR = 16;  // registers per lane per column: rows <= MAXR * G
+  const int nr = (rows + G - 1) / G, nc = (cols + G - 1) / G;
+  int sweep = 0;
+  for (; sweep < 40; ++sweep) {
     if (tid == 0) *flag = 0;
     __syncthreads();
     for (int rd = 0; rd < N - 1; ++rd) {
@@ -278,36 +363,59 @@ __device__ void jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ld
       const bool act = g < P && q < cols;
       Real* a = M + (act ? p : 0) * ldm;
       Real* b = M + (act ? q : 0) * ldm;
+      Real xa[MAXR], xb[MAXR];
       double al = 0, be = 0, ga = 0;  // FP64 sums: no underflow of small columns
-      if (act)
-        for (int r = lane; r < rows; r += G) {
-          const double x = a[r], y = b[r];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
+#pragma unroll
+      for (int j = 0; j < MAXR; ++j) {
+        const int r = lane + j * G;
+        xa[j] = xb[j] = Real(0);
+        if (act && j < nr && r < rows) {
+          xa[j] = a[r];
+          xb[j] = b[r];
         }
-      // all lanes shuffle (wave-uniform); inactive groups reduce zeros
+        al += (double)xa[j] * (double)xa[j];
+        be += (double)xb[j] * (double)xb[j];
+        ga += (double)xa[j] * (double)xb[j];
+      }
       al = group_sum(al, G);
       be = group_sum(be, G);
       ga = group_sum(ga, G);
-      if (act && ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+      const double aga = fabs(ga);
+      const bool rot = act && aga > tol * sqrt(al) * sqrt(be) && aga > keps * (al > be ? al : be) && aga > floor2;
+      if (rot) {
         const double zeta = (be - al) / (2.0 * ga);
-        double tt;
-        if (fabs(zeta) > 1e16) tt = 0.5 / zeta;
-        else tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cd = 1.0 / sqrt(1.0 + tt * tt);
-        const Real c = Real(cd), s = Real(cd * tt);
-        for (int r = lane; r < rows; r += G) {
-          const Real x = a[r], y = b[r];
-          a[r] = c * x - s * y;
-          b[r] = s * x + c * y;
+        Real c, s;
+        if constexpr (sizeof(Real) == 4) {
+          const float z = (float)(zeta > 1e30 ? 1e30 : (zeta < -1e30 ? -1e30 : zeta));
+          const float az = fabsf(z);
+          const float tt = az > 1e15f ? 0.5f / z : (z >= 0.0f ? 1.0f : -1.0f) / (az + sqrtf(1.0f + z * z));
+          c = 1.0f / sqrtf(1.0f + tt * tt);
+          s = c * tt;
+        } else {
+          double tt;
+          if (fabs(zeta) > 1e16) tt = 0.5 / zeta;
+          else tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cd = 1.0 / sqrt(1.0 + tt * tt);
+          c = Real(cd);
+          s = Real(cd * tt);
+        }
+#pragma unroll
+        for (int j = 0; j < MAXR; ++j) {
+          const int r = lane + j * G;
+          if (j < nr && r < rows) {
+            a[r] = c * xa[j] - s * xb[j];
+            b[r] = s * xa[j] + c * xb[j];
+          }
         }
         Real* va = V + p * ldv;
         Real* vb = V + q * ldv;
-        for (int r = lane; r < cols; r += G) {
-          const Real x = va[r], y = vb[r];
-          va[r] = c * x - s * y;
-          vb[r] = s * x + c * y;
+        for (int j = 0; j < nc; ++j) {
+          const int r = lane + j * G;
+          if (r < cols) {
+            const Real x = va[r], y = vb[r];
+            va[r] = c * x - s * y;
+            vb[r] = s * x + c * y;
+          }
         }
         if (lane == 0) *flag = 1;
       }
@@ -315,8 +423,9 @@ __device__ void jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ld
     }
     const int f = *flag;
     __syncthreads();
-    if (!f) break;
+    if (!f) return sweep + 1;
   }
+  return sweep;
 }
 
 }  // namespace tnmld

@@ -221,14 +221,14 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
                                 [&](int i, int j, Real v) { X[i * nn + so * kr + j] = Fac(v); });
         __syncthreads();
       }
-      lq_factor<Fac>(X, mJ, nn, nn, tau, diag, dred);
+      lq_factor_any<Fac>(X, mJ, nn, nn, tau, diag, dred, vtmp);
       // L (mJ x k) for the site to the left
       for (int e = tid; e < mJ * k; e += NT) {
         const int r = e / k, c = e % k;
         L[e] = Real(c < r ? X[r * nn + c] : (c == r ? diag[r] : Fac(0)));
       }
       __syncthreads();
-      lq_form_q<Fac>(X, mJ, nn, nn, tau, vtmp);
+      lq_form_q_any<Fac>(X, mJ, nn, nn, tau, vtmp);
       for (int e = tid; e < k * nn; e += NT) g[e] = Real(X[e]);
       __syncthreads();
     }
@@ -262,14 +262,14 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
       });
       __syncthreads();
       // M^T = Lf Qf (LQ), i.e. M = Qf^T Lf^T: a QR factorisation of M
-      lq_factor<Fac>(Mm, kr, R, ldm, tau, diag, dred);
+      lq_factor_any<Fac>(Mm, kr, R, ldm, tau, diag, dred, vtmp);
       // Lf (kr x k2) -> Lt, column-major (column j at Lt + j*ldl)
       for (int e = tid; e < kr * k2; e += NT) {
         const int r = e / k2, c = e % k2;
         Lt[c * ldl + r] = c < r ? Mm[r * ldm + c] : (c == r ? diag[r] : Fac(0));
       }
       __syncthreads();
-      lq_form_q<Fac>(Mm, kr, R, ldm, tau, vtmp);  // rows 0..k2-1 of Mm: Qf (k2 x R)
+      lq_form_q_any<Fac>(Mm, kr, R, ldm, tau, vtmp);  // rows 0..k2-1 of Mm: Qf (k2 x R)
       if (!cut) {
         // A[(l,so)][r] = Qf[r][(l,so)], carry C[r][c] = Lf[c][r]
         for (int e = tid; e < R * Dn; e += NT) {

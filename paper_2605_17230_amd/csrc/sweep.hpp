@@ -310,6 +310,173 @@ __device__ void lq_form_q(Real* X, int m, int n, int ld, const Real* tau, Real* 
   }
 }
 
+// Register-resident Householder LQ for m <= 64 rows and n <= 256 columns:
+// lane group g (16 lanes) keeps rows g and g + 32 in registers, lane l holds
+// columns l + 16 c.  Same arithmetic and output layout as lq_factor; only the
+// reflector of each step goes through LDS (staged with explicit zeros and the
+// implicit one in vb + (i & 1) * n, so the row update is branch-free).  The
+// owner of row i + 1 builds the next reflector as soon as it has updated that
+// row: one barrier per step.  vb: LDS scratch of 2n.
+constexpr int LQR_RPG = 2, LQR_NPL = 16;
+__device__ inline bool lq_regs_fit(int m, int n) { return m <= LQR_RPG * (NT / 16) && n <= LQR_NPL * 16; }
+
+template <typename Real>
+__device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* diag, double* red, Real* vb) {
+  const int k = m < n ? m : n;
+  const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
+  constexpr int NG = NT / 16;
+  Real x[LQR_RPG][LQR_NPL];
+#pragma unroll
+  for (int j = 0; j < LQR_RPG; ++j) {
+    const int r = grp + NG * j;
+#pragma unroll
+    for (int c = 0; c < LQR_NPL; ++c) {
+      const int col = lane + 16 * c;
+      x[j][c] = (r < m && col < n) ? X[r * ld + col] : Real(0);
+    }
+  }
+  // reflector of row i held in slot j of this group (all 16 lanes call it)
+  auto reflector = [&](int i, Real* xr) {
+    double t2 = 0.0, x0 = 0.0;
+#pragma unroll
+    for (int c = 0; c < LQR_NPL; ++c) {
+      const int col = lane + 16 * c;
+      if (col > i) t2 += (double)xr[c] * (double)xr[c];
+      if (col == i) x0 = (double)xr[c];
+    }
+    t2 = group_sum(t2, 16);
+    x0 = group_sum(x0, 16);  // one lane holds it
+    const double nrm = sqrt(t2 + x0 * x0);
+    const bool live = t2 > 0.0 && nrm > TinyNorm<Real>::v;
+    double beta = x0, t = 0.0, scale = 0.0;
+    if (live) {
+      beta = x0 >= 0.0 ? -nrm : nrm;
+      t = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
+    Real* v = vb + (i & 1) * n;
+#pragma unroll
+    for (int c = 0; c < LQR_NPL; ++c) {
+      const int col = lane + 16 * c;
+      if (live && col > i) xr[c] = Real((double)xr[c] * scale);
+      if (col < n) v[col] = col < i ? Real(0) : (col == i ? Real(1) : xr[c]);
+    }
+    if (lane == 0) {
+      tau[i] = Real(t);
+      diag[i] = Real(beta);
+      red[i & 1] = t;
+    }
+  };
+  if (k > 0 && grp == 0) reflector(0, x[0]);
+  __syncthreads();
+  for (int i = 0; i < k; ++i) {
+    const double t = red[i & 1];
+    const Real* v = vb + (i & 1) * n;
+    Real vv[LQR_NPL];
+#pragma unroll
+    for (int c = 0; c < LQR_NPL; ++c) {
+      const int col = lane + 16 * c;
+      vv[c] = col < n ? v[col] : Real(0);
+    }
+#pragma unroll
+    for (int j = 0; j < LQR_RPG; ++j) {
+      const int r = grp + NG * j;
+      if (r > i && r < m) {
+        if (t != 0.0) {
+          double dot = 0.0;
+#pragma unroll
+          for (int c = 0; c < LQR_NPL; ++c) dot += (double)x[j][c] * (double)vv[c];
+          dot = group_sum(dot, 16);
+          const Real w = Real(dot * t);
+#pragma unroll
+          for (int c = 0; c < LQR_NPL; ++c) x[j][c] -= w * vv[c];
+        }
+        if (r == i + 1 && r < k) reflector(r, x[j]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < LQR_RPG; ++j) {
+    const int r = grp + NG * j;
+#pragma unroll
+    for (int c = 0; c < LQR_NPL; ++c) {
+      const int col = lane + 16 * c;
+      if (r < m && col < n) X[r * ld + col] = x[j][c];
+    }
+  }
+  __syncthreads();
+}
+
+// Register-resident explicit Q after lq_factor (k = min(m, n) <= 64): row r
+// of Q = [I_k 0] H_{k-1} ... H_0 is e_r - tau_r v_r pushed through
+// H_{r-1}, ..., H_0, which involves no other row of Q, so each lane group
+// builds its rows (r and 2*32-1-r, balancing the step counts) with no barrier,
+// reading the reflectors from X.  One barrier before the rows are stored.
+template <typename Real>
+__device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
+  const int k = m < n ? m : n;
+  const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
+  constexpr int NG = NT / 16;
+  Real q[LQR_RPG][LQR_NPL];
+#pragma unroll
+  for (int j = 0; j < LQR_RPG; ++j) {
+    const int r = j == 0 ? grp : 2 * NG - 1 - grp;
+    if (r >= k) continue;
+    {
+      const Real t = tau[r];
+      const Real* xr = X + r * ld;
+#pragma unroll
+      for (int c = 0; c < LQR_NPL; ++c) {
+        const int col = lane + 16 * c;
+        const Real vc = col < r ? Real(0) : (col == r ? Real(1) : (col < n ? xr[col] : Real(0)));
+        q[j][c] = (col == r ? Real(1) : Real(0)) - t * vc;
+      }
+    }
+    for (int i = r - 1; i >= 0; --i) {
+      const Real t = tau[i];
+      if (t == Real(0)) continue;
+      const Real* xi = X + i * ld;
+      Real vv[LQR_NPL];
+      double dot = 0.0;
+#pragma unroll
+      for (int c = 0; c < LQR_NPL; ++c) {
+        const int col = lane + 16 * c;
+        vv[c] = col < i ? Real(0) : (col == i ? Real(1) : (col < n ? xi[col] : Real(0)));
+        dot += (double)q[j][c] * (double)vv[c];
+      }
+      dot = group_sum(dot, 16);
+      const Real w = Real(dot) * t;
+#pragma unroll
+      for (int c = 0; c < LQR_NPL; ++c) q[j][c] -= w * vv[c];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < LQR_RPG; ++j) {
+    const int r = j == 0 ? grp : 2 * NG - 1 - grp;
+    if (r >= k) continue;
+#pragma unroll
+    for (int c = 0; c < LQR_NPL; ++c) {
+      const int col = lane + 16 * c;
+      if (col < n) X[r * ld + col] = q[j][c];
+    }
+  }
+  __syncthreads();
+}
+
+// Dispatch: registers when the matrix fits, else the LDS-resident version.
+template <typename Real>
+__device__ inline void lq_factor_any(Real* X, int m, int n, int ld, Real* tau, Real* diag, double* red, Real* vb) {
+  if (lq_regs_fit(m, n)) lq_factor_regs<Real>(X, m, n, ld, tau, diag, red, vb);
+  else lq_factor<Real>(X, m, n, ld, tau, diag, red);
+}
+template <typename Real>
+__device__ inline void lq_form_q_any(Real* X, int m, int n, int ld, const Real* tau, Real* v) {
+  if (lq_regs_fit(m, n)) lq_form_q_regs<Real>(X, m, n, ld, tau);
+  else lq_form_q<Real>(X, m, n, ld, tau, v);
+}
+
 // One-sided (Hestenes) Jacobi on the columns of M (rows x cols, column-major,
 // leading dimension ldm), accumulating the rotations in V (cols x cols,
 // column-major, ldv), which must hold the identity on entry.  Afterwards the

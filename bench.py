@@ -1,13 +1,16 @@
 """Throughput of batched boundary-MPS coset decoding on one MI355X.
 
-Workload: rotated surface code d = 17 under depolarizing noise p = 0.12,
-16,384 seeded synthetic syndromes, bond dimension chi = 32, four cosets per
-syndrome.  One step = decode the whole batch (every row MPO, LQ sweep and
-truncation sweep of all 65,536 contractions, then the per-syndrome decision),
-inputs already resident in HBM.  Prints one JSON line.
+Default workload: rotated surface code d = 17 under depolarizing noise
+p = 0.12, 16,384 seeded synthetic syndromes, bond dimension chi = 32, four
+cosets per syndrome.  One step = decode the whole batch (row MPOs, LQ sweeps
+and truncation sweeps of all 65,536 contractions, then the per-syndrome
+decision) with inputs already resident in HBM.  The timed form is the BF16
+form (bf16 MFMA contractions, FP32 factorisations); the plain FP32 form is
+timed once beside it, and both are compared with the FP64 form on a sample.
+Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--precision fp32plain|fp32|fp64]
-                  [--compare fp32plain] [--cpu-seconds S] [--no-cpu]
+  python bench.py [--steps K] [--warmup W] [--precision bf16|fp32plain|fp32|fp64]
+                  [--compare fp32plain] [--workload c3|c4] [--cpu-seconds S] [--no-cpu]
 """
 import argparse
 import json
@@ -21,7 +24,9 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 D, CHI, P, COUNT, SEED = 17, 32, 0.12, 16384, 3000
-PEAK_ALU_TFLOPS = 78.6  # MI355X: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP64 / non-packed FP32 FMA)
+# MI355X non-packed VALU peak: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz;
+# FP64 runs at the same rate.
+PEAK_ALU_TFLOPS = 78.6
 
 
 def parse():
@@ -29,9 +34,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32plain")
-    ap.add_argument("--compare", default="")
+    ap.add_argument("--precision", default="bf16")
+    ap.add_argument("--compare", default="fp32plain", help="second form timed once ('' to skip)")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4"])
     ap.add_argument("--count", type=int, default=COUNT)
+    ap.add_argument("--fp64-sample", type=int, default=512, help="syndromes decoded in FP64 for the error report")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -50,23 +57,26 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}), flush=True)
 
 
-def cpu_baseline(syn, rates, target_s):
+def cpu_baseline(d, rates, syn, target_s):
     """FP64 oracle (exact transfer-matrix contraction) on a bounded prefix."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     n = max(threads, 1)
     t0 = time.time()
-    ref = oracle.transfer(D, rates, syn[:n], threads=threads)
+    ref = oracle.transfer(d, rates, syn[:n], threads=threads)
     dt = time.time() - t0
     per = dt / n * threads  # seconds per syndrome per thread
     more = int(max(0, target_s - dt) / max(per, 1e-9) * threads) // threads * threads
     if more > 0:
         t1 = time.time()
-        ref2 = oracle.transfer(D, rates, syn[n:n + more], threads=threads)
+        ref2 = oracle.transfer(d, rates, syn[n:n + more], threads=threads)
         dt += time.time() - t1
         ref = np.concatenate([ref, ref2])
         n += more
     return ref, n, dt, threads
+
+
+DTYPE = {"fp32plain": "f32", "fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32"}
 
 
 def main():
@@ -84,29 +94,44 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
-    rates = synth.depolarizing(D, P)
-    smp = synth.sample(D, rates, a.count, SEED)
-    syn_h = smp["syndromes"]
-    syn = torch.from_numpy(syn_h).to(dev)
-    rt = torch.from_numpy(rates).to(dev)
-    info = tn.plan_info(D, CHI, a.precision)
-    flops_per_step = 4.0 * a.count * info["flops"]
     stream = torch.cuda.current_stream(dev)
+    if a.workload == "c3":
+        rates = synth.depolarizing(D, P)
+        smp = synth.sample(D, rates, a.count, SEED)
+        segs_h = [dict(d=D, chi=CHI, syndromes=smp["syndromes"], rates=rates,
+                       model_index=np.zeros(a.count, np.int32))]
+        workload = "rotated surface code d=17, depolarizing p=0.12, %d seeded syndromes, chi=32" % a.count
+    else:
+        segs_h = synth.config_inputs("C4")
+        workload = ("mixed batch in one launch: d=5..15 with 32768..1024 syndromes, biased p=0.08, "
+                    "eta in {1,10,100}, chi=8..28")
+    n_syn = sum(len(s["syndromes"]) for s in segs_h)
+    dev_in = [(torch.from_numpy(s["syndromes"]).to(dev), torch.from_numpy(s["rates"]).to(dev),
+               torch.from_numpy(s["model_index"]).to(dev)) for s in segs_h]
 
-    def step(prec):
-        return tn.decode(syn, rt, D, CHI, prec)
+    def inputs(prec, limit=None):
+        out = []
+        for s, (sy, rt, mi) in zip(segs_h, dev_in):
+            if limit is not None:
+                sy, mi = sy[:limit], mi[:limit]
+            out.append(tn.SegmentInput(s["d"], s["chi"], sy, rt, mi, prec))
+        return out
 
-    print("bench: d=%d chi=%d %s, %d syndromes, %d warmup + %d timed steps"
-          % (D, CHI, a.precision, a.count, a.warmup, a.steps), file=sys.stderr, flush=True)
+    flops_per_step = sum(4.0 * len(s["syndromes"]) * tn.plan_info(s["d"], s["chi"], a.precision)["flops"]
+                         for s in segs_h)
+    segs = inputs(a.precision)
+    print("bench: %s, %s, %d warmup + %d timed steps" % (workload, a.precision, a.warmup, a.steps),
+          file=sys.stderr, flush=True)
     for _ in range(a.warmup):
-        step(a.precision)
+        tn.decode_segments(segs)
     torch.cuda.synchronize()
     ev = []
     t0 = time.time()
+    outs = None
     for i in range(a.steps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        logz, logp, cls = step(a.precision)
+        outs = tn.decode_segments(segs)
         e1.record(stream)
         ev.append((e0, e1))
         print("bench: step %d enqueued" % i, file=sys.stderr, flush=True)
@@ -114,10 +139,11 @@ def main():
     wall = time.time() - t0
     ms = [e0.elapsed_time(e1) for e0, e1 in ev]
     ms_step = float(np.mean(ms))
-    value = a.count / (ms_step / 1e3)
+    value = n_syn / (ms_step / 1e3)
     achieved = flops_per_step / (ms_step / 1e3) / 1e12
     out = {
-        "metric": "syndromes/s at d=17 chi=32 (boundary-MPS coset decoding)",
+        "metric": "syndromes/s at d=17 chi=32 (boundary-MPS coset decoding), BF16 form vs FP32 plain; "
+                  "coset log-likelihood error vs FP64",
         "value": value,
         "unit": "syndromes/s",
         "n_gpus": 1,
@@ -127,41 +153,67 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32plain": "f32", "fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f64"}[a.precision],
+        "dtype": DTYPE[a.precision],
         "data": "synthetic",
-        "config": {"workload": "rotated surface code d=17, depolarizing p=0.12, 16384 seeded syndromes, chi=32",
-                   "d": D, "chi": CHI, "p": P, "syndromes": a.count, "cosets": 4, "precision": a.precision},
+        "config": {"workload": workload, "syndromes": n_syn, "cosets": 4, "precision": a.precision,
+                   "segments": [{"d": s["d"], "chi": s["chi"], "count": len(s["syndromes"])} for s in segs_h]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
                      "flops_per_launch": flops_per_step, "kernel": "fwd_kernel"},
         "wall_s": wall,
     }
-    logz_h = logz.cpu().numpy()
-    cls_h = cls.cpu().numpy()
-    if a.compare:
+    print("bench: timed %.1f ms per step" % ms_step, file=sys.stderr, flush=True)
+    lz = [o.logz.cpu().numpy() for o in outs]
+    cls = [o.cls.cpu().numpy() for o in outs]
+    o2 = None
+    if a.compare and a.compare != a.precision:
+        s2 = inputs(a.compare)
+        tn.decode_segments(s2)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        lz2, _, c2 = step(a.compare)
+        o2 = tn.decode_segments(s2)
         e1.record(stream)
         torch.cuda.synchronize()
         ms2 = e0.elapsed_time(e1)
-        out["compare"] = {"precision": a.compare, "value": a.count / (ms2 / 1e3), "ms_per_step": ms2,
-                          "speedup": ms2 / ms_step,
-                          "max_abs_dlogz_vs_primary": float(np.max(np.abs(lz2.cpu().numpy() - logz_h))),
-                          "class_agreement": float((c2.cpu().numpy() == cls_h).mean())}
-    if not a.no_cpu:
+        out["compare"] = {"precision": a.compare, "value": n_syn / (ms2 / 1e3), "ms_per_step": ms2,
+                          "speedup_of_primary": ms2 / ms_step,
+                          "max_abs_dlogz_vs_primary": float(max(np.max(np.abs(x.logz.cpu().numpy() - y))
+                                                                for x, y in zip(o2, lz))),
+                          "class_agreement_with_primary": float(np.mean(np.concatenate(
+                              [x.cls.cpu().numpy() == y for x, y in zip(o2, cls)])))}
+        print("bench: compare %s %.1f ms" % (a.compare, ms2), file=sys.stderr, flush=True)
+    if a.fp64_sample > 0 and a.workload == "c3":
+        ns = min(a.fp64_sample, n_syn)
+        o64 = tn.decode_segments(inputs("fp64", ns))[0]
+        ref64 = o64.logz.cpu().numpy()
+        c64 = o64.cls.cpu().numpy()
+        err = {"syndromes": ns, "chi": CHI}
+        forms = [(a.precision, lz[0][:ns], cls[0][:ns])]
+        if o2 is not None:
+            forms.append((a.compare, o2[0].logz.cpu().numpy()[:ns], o2[0].cls.cpu().numpy()[:ns]))
+        for name, z, c in forms:
+            fin = np.isfinite(ref64)
+            err[name] = {"max_abs_dlogz": float(np.max(np.abs(np.where(fin, z - ref64, 0.0)))),
+                         "max_abs_dlogp": float(np.max(np.abs(np.logaddexp.reduce(z, 1)
+                                                              - np.logaddexp.reduce(ref64, 1)))),
+                         "class_agreement": float(np.mean(c == c64))}
+        out["error_vs_fp64_same_chi"] = err
+        print("bench: fp64 sample done", file=sys.stderr, flush=True)
+    if not a.no_cpu and a.workload == "c3":
         import oracle
-        ref, n, dt, threads = cpu_baseline(syn_h, rates, a.cpu_seconds)
+        s0 = segs_h[0]
+        ref, n, dt, threads = cpu_baseline(D, s0["rates"], s0["syndromes"], a.cpu_seconds)
         _, rcls = oracle.decide(ref)
-        err = np.abs(logz_h[:n] - ref)
+        fin = np.isfinite(ref)
         out["cpu_baseline"] = {"value": n / dt, "unit": "syndromes/s", "cores": threads, "kind": "oracle",
                                "sample": "first %d syndromes of the batch, exact FP64 transfer-matrix "
                                          "contraction (4 cosets each), %.1f s" % (n, dt)}
-        out["parity_vs_oracle"] = {"syndromes": n, "max_abs_dlogz": float(err.max()),
+        out["parity_vs_oracle"] = {"syndromes": n,
+                                   "max_abs_dlogz": float(np.max(np.where(fin, np.abs(lz[0][:n] - ref), 0.0))),
                                    "max_abs_dlogp": float(np.max(np.abs(
-                                       np.logaddexp.reduce(logz_h[:n], 1) - np.logaddexp.reduce(ref, 1)))),
-                                   "class_agreement": float((cls_h[:n] == rcls).mean())}
+                                       np.logaddexp.reduce(lz[0][:n], 1) - np.logaddexp.reduce(ref, 1)))),
+                                   "class_agreement": float((cls[0][:n] == rcls).mean())}
     print(json.dumps(out), flush=True)
 
 

@@ -255,7 +255,7 @@ __device__ void adjoint_one(const JobDev& job, int64_t b, int mlog, uint8_t* sme
   for (int u = 0; u < nstep; ++u) {
     const SiteStep* row = steps + (int64_t)u * nsite;
     if (u % kseg == 0) mps_pack(top, region, nsite, in_dims(row), cps + (int64_t)(u / kseg) * me, false, top);
-    if (!row_step<Real, Fac, GM>(row, nsite, codes, rates, top, region, w, logscale)) return;
+    if (!row_step_outlined<Real, Fac, GM>(row, nsite, codes, rates, top, region, w, logscale)) return;
   }
   // --- bottom-up, recomputing each segment of top states -------------------
   {
@@ -273,7 +273,7 @@ __device__ void adjoint_one(const JobDev& job, int64_t b, int mlog, uint8_t* sme
       mps_pack(top, region, nsite, in_dims(steps + (int64_t)t0 * nsite), cps + (int64_t)c * me, true, top);
       mps_pack(top, region, nsite, in_dims(steps + (int64_t)t0 * nsite), seg, false, top);
       for (int t = t0; t + 1 < t1; ++t) {
-        if (!row_step<Real, Fac, GM>(steps + (int64_t)t * nsite, nsite, codes, rates, top, region, w, logscale)) return;
+        if (!row_step_outlined<Real, Fac, GM>(steps + (int64_t)t * nsite, nsite, codes, rates, top, region, w, logscale)) return;
         mps_pack(top, region, nsite, in_dims(steps + (int64_t)(t + 1) * nsite), seg + (int64_t)(t + 1 - t0) * me, false,
                  top);
       }
@@ -283,7 +283,7 @@ __device__ void adjoint_one(const JobDev& job, int64_t b, int mlog, uint8_t* sme
     const SiteStep* brow = bsteps + (int64_t)(nstep - 1 - u) * nsite;
     row_gradient<Real>(frow, brow, nsite, codes, rates, w.fbits, seg + (int64_t)(u - c * kseg) * me, bot, region, env, P1,
                        P2, P3, w.Wv, weight, pm);
-    if (u > 0 && !row_step<Real, Fac, GM>(brow, nsite, codes, rates, bot, region, w, bscale)) return;
+    if (u > 0 && !row_step_outlined<Real, Fac, GM>(brow, nsite, codes, rates, bot, region, w, bscale)) return;
   }
 }
 

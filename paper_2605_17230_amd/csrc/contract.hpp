@@ -337,6 +337,16 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
   return alive;
 }
 
+// Out-of-line copy of row_step for callers that run it from several places
+// (the adjoint): one body instead of three inlined ones keeps register
+// pressure, and with it spilling, down.
+template <typename Real, typename Fac, int GM>
+__device__ __attribute__((noinline)) bool row_step_outlined(const SiteStep* row, int nsite, const uint8_t* codes,
+                                                            const double* rates, Real* scr, const int64_t* region,
+                                                            Work<Real, Fac>& w, double& logscale) {
+  return row_step<Real, Fac, GM>(row, nsite, codes, rates, scr, region, w, logscale);
+}
+
 // Sum of the MPS over every physical index (the closing all-ones boundary);
 // returns log of it (FP64), -inf when not positive.  Collective.
 template <typename Real, typename Fac>

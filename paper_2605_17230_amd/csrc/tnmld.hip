@@ -174,7 +174,7 @@ bool precision_built(int precision) {
 constexpr int kLdsLimit = 160 * 1024;
 
 constexpr int kLdsPerCU = 160 * 1024;
-constexpr int kMaxWgPerCU = 1024 / NT > 1 ? 1024 / NT : 1;  // <= 128 VGPRs: 4 waves per SIMD, 1024 threads per CU
+constexpr int kMaxWgPerCU = 1024 / NT > 1 ? 1024 / NT : 1;  // 4 waves per SIMD at most for 512-thread groups
 
 // Tuned launch shapes, set by tn_set_tuning (the autotuner's cache).
 struct Tune {
@@ -182,9 +182,55 @@ struct Tune {
 };
 std::map<std::tuple<int, int, int>, Tune> g_tune;
 
-int wgs_for(int lds_bytes) {
-  const int w = kLdsPerCU / (lds_bytes + 256);
-  return w < 1 ? 0 : (w > kMaxWgPerCU ? kMaxWgPerCU : w);
+// Raise a kernel's dynamic-LDS limit once per (kernel, size) and remember it,
+// so that warm calls enqueue kernels only (a stream being captured into a
+// graph sees no attribute calls).
+int ensure_lds_attr(const void* kern, int bytes) {
+  static std::map<const void*, int> done;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  int& cur = done[kern];
+  if (cur >= bytes) return TN_OK;
+  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
+    return fail(TN_EDEVICE, "hipFuncSetAttribute failed");
+  cur = bytes;
+  return TN_OK;
+}
+
+const void* fwd_kernel_of(int precision) {
+  if (precision == TN_FP64) return reinterpret_cast<const void*>(fwd_kernel<double, double, GEMM_VALU>);
+  if (precision == TN_FP32) return reinterpret_cast<const void*>(fwd_kernel<float, double, GEMM_VALU>);
+  if (precision == TN_BF16) return reinterpret_cast<const void*>(fwd_kernel<float, float, BF16_GEMM_MODE>);
+  return reinterpret_cast<const void*>(fwd_kernel<float, float, GEMM_VALU>);
+}
+const void* bwd_kernel_of(int precision) {
+  if (precision == TN_FP64) return reinterpret_cast<const void*>(bwd_kernel<double, double, GEMM_VALU>);
+  if (precision == TN_FP32) return reinterpret_cast<const void*>(bwd_kernel<float, double, GEMM_VALU>);
+  if (precision == TN_BF16) return reinterpret_cast<const void*>(bwd_kernel<float, float, BF16_GEMM_MODE>);
+  return reinterpret_cast<const void*>(bwd_kernel<float, float, GEMM_VALU>);
+}
+
+// Work-groups of `kern` that one CU holds at once with lds_bytes of dynamic
+// LDS: the smaller of the LDS fit and the register-file fit reported by the
+// runtime (the sweep kernels use up to 256 VGPRs, i.e. one 512-thread group
+// per CU).  Without a device only the LDS fit is known.
+int wgs_for(int lds_bytes, const void* kern = nullptr) {
+  int w = kLdsPerCU / (lds_bytes + 256);
+  w = w < 1 ? 0 : (w > kMaxWgPerCU ? kMaxWgPerCU : w);
+  if (!kern || w == 0) return w;
+  static std::map<std::pair<const void*, int>, int> cache;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_pair(kern, lds_bytes);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    int nb = 0;
+    if (ensure_lds_attr(kern, lds_bytes) != TN_OK ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, (size_t)lds_bytes) != hipSuccess || nb < 1)
+      nb = w;
+    it = cache.emplace(key, nb).first;
+  }
+  return std::min(w, it->second);
 }
 
 // Choose the column grouping (1 or 2 columns per site): a tuned entry if one
@@ -211,7 +257,7 @@ int choose_group(int d, int chi, int precision, int lds_limit, Plan* out, std::s
       *why = "chi=" + std::to_string(chi) + " needs " + std::to_string(lay.bytes) + " B of LDS";
       continue;
     }
-    const int w = wgs_for(lay.bytes);
+    const int w = wgs_for(lay.bytes, fwd_kernel_of(precision));
     if (w > best_w) {
       best_w = w;
       best_g = g;
@@ -327,7 +373,7 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
   for (auto& L : *out) {
     if (L.merged.max_bond > NT) return fail(TN_EUNSUPPORTED, "bond dimension above the work-group size");
     const int lb = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision)).bytes;
-    int w = wgs_for(lb);
+    int w = wgs_for(lb, fwd_kernel_of(L.precision));
     if (L.nwg > 0) w = std::min(w, L.nwg);
     if (w < 1) return fail(TN_EUNSUPPORTED, "LDS of the merged plans exceeds one CU");
     L.nwg = w * di.cus;
@@ -342,9 +388,7 @@ template <typename Real, typename Fac, int GM>
 int launch_fwd(const Launch& L, int nwg, char* ws_scratch, unsigned long long* counter, hipStream_t st) {
   LdsLayout lay = lds_layout(L.merged, sizeof(Real), sizeof(Fac));
   auto kern = fwd_kernel<Real, Fac, GM>;
-  if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          lay.bytes) != hipSuccess)
-    return fail(TN_EDEVICE, "hipFuncSetAttribute failed");
+  if (int rc = ensure_lds_attr(reinterpret_cast<const void*>(kern), lay.bytes)) return rc;
   zero_counter<<<1, 64, 0, st>>>(counter);
   const int64_t stride = (int64_t)align_up((size_t)L.scratch_elems * sizeof(Real));
   hipLaunchKernelGGL(kern, dim3(nwg), dim3(NT), lay.bytes, st, L.jt, counter, ws_scratch, stride, lay);
@@ -454,7 +498,7 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
                                                H->env_elems + 3 * H->tmp_elems);
   }
   const int lb = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision)).bytes;
-  bl->nwg = std::max(1, wgs_for(lb)) * di.cus;
+  bl->nwg = std::max(1, wgs_for(lb, bwd_kernel_of(L.precision))) * di.cus;
   bl->scratch_stride = (int64_t)align_up((size_t)per_item * real_bytes(L.precision));
   bl->part_stride = (part + 31) / 32 * 32;
   bl->total = bl->fwd_bytes + align_up((size_t)bl->nwg * bl->part_stride * sizeof(double)) +
@@ -537,8 +581,7 @@ int tn_coset_loglik_backward(const tn_segment* segs, int32_t nseg, const double*
   else if (bl.precision == TN_FP32) kern = reinterpret_cast<const void*>(bwd_kernel<float, double, GEMM_VALU>);
   else if (bl.precision == TN_BF16) kern = reinterpret_cast<const void*>(bwd_kernel<float, float, BF16_GEMM_MODE>);
   else kern = reinterpret_cast<const void*>(bwd_kernel<float, float, GEMM_VALU>);
-  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, lay.bytes) != hipSuccess)
-    return fail(TN_EDEVICE, "hipFuncSetAttribute failed");
+  if ((rc = ensure_lds_attr(kern, lay.bytes))) return rc;
   int kseg = bl.kseg;
   int64_t sstride = bl.scratch_stride, pstride = bl.part_stride;
   void* args[] = {&jt, &scratch, &sstride, &lay, &kseg, &partials, &pstride};
@@ -590,7 +633,7 @@ int tn_plan_info(int32_t d, int32_t chi, int32_t precision, double* info) {
   info[3] = p.h.nsite;
   info[4] = p.h.nstep;
   info[5] = g;
-  info[6] = wgs_for((int)info[2]);
+  info[6] = wgs_for((int)info[2], fwd_kernel_of(precision));
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_tune.find(std::make_tuple(d, chi, precision));

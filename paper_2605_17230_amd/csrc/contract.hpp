@@ -78,6 +78,7 @@ struct Work {
   uint8_t* syn;
   int* perm;
   double* dred;
+  double* nrm;
   Real *Wv, *Aj, *T, *L, *C;
   Fac *X, *tau, *diag, *vtmp, *Mm, *Vv, *Lt, *sig;
   int* s_flag;
@@ -91,6 +92,7 @@ __device__ inline Work<Real, Fac> carve(uint8_t* smem, const LdsLayout& lay, int
   w.syn = smem + lay.syn;
   w.perm = reinterpret_cast<int*>(smem + lay.perm);
   w.dred = reinterpret_cast<double*>(smem + lay.red);
+  w.nrm = reinterpret_cast<double*>(smem + lay.nrm);
   w.Wv = reinterpret_cast<Real*>(smem + lay.W);
   w.Aj = reinterpret_cast<Real*>(smem + lay.Aj);
   w.T = reinterpret_cast<Real*>(smem + lay.T);
@@ -298,7 +300,7 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
         // M = (Qf^T W) S U'^T; keep the Dn largest singular values
         for (int e = tid; e < k2 * k2; e += NT) Vv[(e / k2) * ldl + (e % k2)] = (e / k2 == e % k2) ? Fac(1) : Fac(0);
         __syncthreads();
-        jacobi_svd<Fac>(Lt, kr, k2, ldl, Vv, ldl, SplitTol<Fac>::v, w.s_flag, dred);
+        jacobi_svd<Fac>(Lt, kr, k2, ldl, Vv, ldl, SplitTol<Fac>::v, w.s_flag, dred, w.nrm);
         for (int c = tid; c < k2; c += NT) {
           double s2 = 0;
           for (int r = 0; r < kr; ++r) s2 += (double)Lt[c * ldl + r] * (double)Lt[c * ldl + r];

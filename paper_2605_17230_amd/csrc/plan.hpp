@@ -116,6 +116,7 @@ struct LdsLayout {
   int32_t tau, diag, v;               // Householder scalars and reflector (both phases)
   int32_t W;                          // MPO values of the current site (<= 64, storage type)
   int32_t red, perm, rank, fbits, syn;  // FP64 reduction scratch, kept columns, column sets, reference-error bits, syndrome
+  int32_t nrm;                         // FP64 squared column norms of the truncation SVD
   int32_t bytes;
 };
 
@@ -144,6 +145,7 @@ inline LdsLayout lds_layout(const PlanHeader& h, int rb, int fb) {
   o.v = p; p += pad64b((int64_t)2 * nv * fb);
   o.W = p; p += pad64b(64 * rb);
   o.red = p; p += 64 * 8;
+  o.nrm = p; p += pad64b((int64_t)(h.max_kr > h.max_bond ? h.max_kr : h.max_bond) * 8);
   o.perm = p; p += pad64b((int64_t)h.max_kr * 4);
   o.fbits = p; p += pad64b(h.n);
   o.syn = p; p += pad64b(h.m);

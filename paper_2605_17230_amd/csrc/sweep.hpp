@@ -337,14 +337,14 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
   }
   // reflector of row i held in slot j of this group (all 16 lanes call it)
   auto reflector = [&](int i, Real* xr) {
-    double t2 = 0.0, x0 = 0.0;
+    double tp[4] = {0.0, 0.0, 0.0, 0.0}, x0 = 0.0;  // four partial sums: short FMA chains
 #pragma unroll
     for (int c = 0; c < LQR_NPL; ++c) {
       const int col = lane + 16 * c;
-      if (col > i) t2 += (double)xr[c] * (double)xr[c];
+      if (col > i) tp[c & 3] += (double)xr[c] * (double)xr[c];
       if (col == i) x0 = (double)xr[c];
     }
-    t2 = group_sum(t2, 16);
+    double t2 = group_sum((tp[0] + tp[1]) + (tp[2] + tp[3]), 16);
     x0 = group_sum(x0, 16);  // one lane holds it
     const double nrm = sqrt(t2 + x0 * x0);
     const bool live = t2 > 0.0 && nrm > TinyNorm<Real>::v;
@@ -383,10 +383,10 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
       const int r = grp + NG * j;
       if (r > i && r < m) {
         if (t != 0.0) {
-          double dot = 0.0;
+          double dp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int c = 0; c < LQR_NPL; ++c) dot += (double)x[j][c] * (double)vv[c];
-          dot = group_sum(dot, 16);
+          for (int c = 0; c < LQR_NPL; ++c) dp[c & 3] += (double)x[j][c] * (double)vv[c];
+          const double dot = group_sum((dp[0] + dp[1]) + (dp[2] + dp[3]), 16);
           const Real w = Real(dot * t);
 #pragma unroll
           for (int c = 0; c < LQR_NPL; ++c) x[j][c] -= w * vv[c];
@@ -438,14 +438,14 @@ __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
       if (t == Real(0)) continue;
       const Real* xi = X + i * ld;
       Real vv[LQR_NPL];
-      double dot = 0.0;
+      double dp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int c = 0; c < LQR_NPL; ++c) {
         const int col = lane + 16 * c;
         vv[c] = col < i ? Real(0) : (col == i ? Real(1) : (col < n ? xi[col] : Real(0)));
-        dot += (double)q[j][c] * (double)vv[c];
+        dp[c & 3] += (double)q[j][c] * (double)vv[c];
       }
-      dot = group_sum(dot, 16);
+      const double dot = group_sum((dp[0] + dp[1]) + (dp[2] + dp[3]), 16);
       const Real w = Real(dot) * t;
 #pragma unroll
       for (int c = 0; c < LQR_NPL; ++c) q[j][c] -= w * vv[c];
@@ -494,7 +494,7 @@ __device__ inline void lq_form_q_any(Real* X, int m, int n, int ld, const Real* 
 // rotating forever.  Returns the number of sweeps.
 template <typename Real>
 __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv, double tol, int* flag,
-                          double* red) {
+                          double* red, double* nrm) {
   if (cols < 2) return 0;
   const int N = cols + (cols & 1);
   const int P = N >> 1;
@@ -512,6 +512,16 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
   int sweep = 0;
   for (; sweep < 40; ++sweep) {
     if (tid == 0) *flag = 0;
+    // exact squared column norms at the start of every sweep; rotations then
+    // update them in closed form (|a'|^2 = |a|^2 - t a.b, |b'|^2 = |b|^2 + t a.b)
+    for (int c0 = 0; c0 < cols; c0 += NT / G) {
+      const int c = c0 + g;
+      double sq = 0;
+      if (c < cols)
+        for (int r = lane; r < rows; r += G) sq += (double)M[c * ldm + r] * (double)M[c * ldm + r];
+      sq = group_sum(sq, G);
+      if (c < cols && lane == 0) nrm[c] = sq;
+    }
     __syncthreads();
     for (int rd = 0; rd < N - 1; ++rd) {
       int p, q;
@@ -531,7 +541,7 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
       Real* a = M + (act ? p : 0) * ldm;
       Real* b = M + (act ? q : 0) * ldm;
       Real xa[MAXR], xb[MAXR];
-      double al = 0, be = 0, ga = 0;  // FP64 sums: no underflow of small columns
+      double gp[2] = {0.0, 0.0};  // FP64 sums: no underflow of small columns
 #pragma unroll
       for (int j = 0; j < MAXR; ++j) {
         const int r = lane + j * G;
@@ -540,31 +550,34 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
           xa[j] = a[r];
           xb[j] = b[r];
         }
-        al += (double)xa[j] * (double)xa[j];
-        be += (double)xb[j] * (double)xb[j];
-        ga += (double)xa[j] * (double)xb[j];
+        gp[j & 1] += (double)xa[j] * (double)xb[j];
       }
-      al = group_sum(al, G);
-      be = group_sum(be, G);
-      ga = group_sum(ga, G);
+      const double al = act ? nrm[p] : 0.0, be = act ? nrm[q] : 0.0;
+      const double ga = group_sum(gp[0] + gp[1], G);
       const double aga = fabs(ga);
-      const bool rot = act && aga > tol * sqrt(al) * sqrt(be) && aga > keps * (al > be ? al : be) && aga > floor2;
+      // squared form of |ga| > tol |a| |b| (the pair is far above the noise floor here)
+      const bool rot = act && aga > keps * (al > be ? al : be) && aga > floor2 && ga * ga > tol * tol * al * be &&
+                       (sizeof(Real) == 8 || (float)ga != 0.0f);
       if (rot) {
-        const double zeta = (be - al) / (2.0 * ga);
         Real c, s;
+        double tn;
         if constexpr (sizeof(Real) == 4) {
-          const float z = (float)(zeta > 1e30 ? 1e30 : (zeta < -1e30 ? -1e30 : zeta));
+          // the rotation of FP32 columns only needs an FP32 angle
+          const float z = (float)(be - al) / (2.0f * (float)ga);
           const float az = fabsf(z);
           const float tt = az > 1e15f ? 0.5f / z : (z >= 0.0f ? 1.0f : -1.0f) / (az + sqrtf(1.0f + z * z));
           c = 1.0f / sqrtf(1.0f + tt * tt);
           s = c * tt;
+          tn = (double)tt;
         } else {
+          const double zeta = (be - al) / (2.0 * ga);
           double tt;
           if (fabs(zeta) > 1e16) tt = 0.5 / zeta;
           else tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cd = 1.0 / sqrt(1.0 + tt * tt);
           c = Real(cd);
           s = Real(cd * tt);
+          tn = tt;
         }
 #pragma unroll
         for (int j = 0; j < MAXR; ++j) {
@@ -584,7 +597,11 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
             vb[r] = s * x + c * y;
           }
         }
-        if (lane == 0) *flag = 1;
+        if (lane == 0) {
+          *flag = 1;
+          nrm[p] = fmax(al - tn * ga, 0.0);
+          nrm[q] = fmax(be + tn * ga, 0.0);
+        }
       }
       __syncthreads();
     }

@@ -491,10 +491,13 @@ __device__ inline void lq_form_q_any(Real* X, int m, int n, int ld, const Real* 
 // larger one is noise of the larger), or |a.b| <= (k eps |M|_F)^2 (both
 // columns are noise of the matrix), with k = sqrt(rows).  Without the last
 // two tests, columns at the rounding floor of a strongly graded matrix keep
-// rotating forever.  Returns the number of sweeps.
+// rotating forever.  The iteration stops after a sweep in which no rotated
+// pair had a cosine above sqrt(tol / cols): with quadratic convergence the
+// pairs are then below tol.  Returns the number of sweeps.
 template <typename Real>
 __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv, double tol, int* flag,
                           double* red, double* nrm) {
+  constexpr int MAXR = 4;  // rows (and V rows) lane + j G, j < MAXR, live in registers; the rest stream from LDS
   if (cols < 2) return 0;
   const int N = cols + (cols & 1);
   const int P = N >> 1;
@@ -507,8 +510,10 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
   const double nf2 = block_sum(part, red);
   const double keps = sqrt((double)rows) * (double)Eps<Real>::v;
   const double floor2 = keps * keps * nf2;
-  constexpr int MAXR = 16;  // registers per lane per column: rows <= MAXR * G
   const int nr = (rows + G - 1) / G, nc = (cols + G - 1) / G;
+  // a sweep whose largest rotated cosine is below sqrt(tol / cols) leaves every
+  // pair below tol (convergence is quadratic), so no confirming sweep follows
+  const double big2 = tol / (double)cols;
   int sweep = 0;
   for (; sweep < 40; ++sweep) {
     if (tid == 0) *flag = 0;
@@ -552,6 +557,21 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
         }
         gp[j & 1] += (double)xa[j] * (double)xb[j];
       }
+      if (act)
+        for (int r = lane + MAXR * G; r < rows; r += G) gp[0] += (double)a[r] * (double)b[r];
+      // the rotation's V columns are loaded now so that their latency overlaps the reduction
+      Real* va = V + (act ? p : 0) * ldv;
+      Real* vb = V + (act ? q : 0) * ldv;
+      Real ya[MAXR], yb[MAXR];
+#pragma unroll
+      for (int j = 0; j < MAXR; ++j) {
+        const int r = lane + j * G;
+        ya[j] = yb[j] = Real(0);
+        if (act && j < nc && r < cols) {
+          ya[j] = va[r];
+          yb[j] = vb[r];
+        }
+      }
       const double al = act ? nrm[p] : 0.0, be = act ? nrm[q] : 0.0;
       const double ga = group_sum(gp[0] + gp[1], G);
       const double aga = fabs(ga);
@@ -587,18 +607,26 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
             b[r] = s * xa[j] + c * xb[j];
           }
         }
-        Real* va = V + p * ldv;
-        Real* vb = V + q * ldv;
-        for (int j = 0; j < nc; ++j) {
+        for (int r = lane + MAXR * G; r < rows; r += G) {
+          const Real x = a[r], y = b[r];
+          a[r] = c * x - s * y;
+          b[r] = s * x + c * y;
+        }
+#pragma unroll
+        for (int j = 0; j < MAXR; ++j) {
           const int r = lane + j * G;
-          if (r < cols) {
-            const Real x = va[r], y = vb[r];
-            va[r] = c * x - s * y;
-            vb[r] = s * x + c * y;
+          if (j < nc && r < cols) {
+            va[r] = c * ya[j] - s * yb[j];
+            vb[r] = s * ya[j] + c * yb[j];
           }
         }
+        for (int r = lane + MAXR * G; r < cols; r += G) {
+          const Real x = va[r], y = vb[r];
+          va[r] = c * x - s * y;
+          vb[r] = s * x + c * y;
+        }
         if (lane == 0) {
-          *flag = 1;
+          if (ga * ga > big2 * al * be) *flag = 1;
           nrm[p] = fmax(al - tn * ga, 0.0);
           nrm[q] = fmax(be + tn * ga, 0.0);
         }
@@ -611,5 +639,6 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
   }
   return sweep;
 }
+
 
 }  // namespace tnmld

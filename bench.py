@@ -79,6 +79,32 @@ def cpu_baseline(d, rates, syn, target_s):
 DTYPE = {"fp32plain": "f32", "fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32"}
 
 
+def kernel_sources_sha256():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2605_17230_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision, count, workload):
+    """HBM bytes per launch from the committed counter runs, only when they were
+    taken on these exact kernel sources, precision and batch; else None."""
+    import glob
+    if workload != "c3":
+        return None
+    sha = kernel_sources_sha256()
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json")):
+        with open(f) as fh:
+            r = json.load(fh)
+        if r.get("sources_sha256") == sha and r.get("precision") == precision and r.get("count") == count:
+            return float(r["traffic_bytes_per_launch"])
+    return None
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -158,7 +184,8 @@ def main():
         "config": {"workload": workload, "syndromes": n_syn, "cosets": 4, "precision": a.precision,
                    "segments": [{"d": s["d"], "chi": s["chi"], "count": len(s["syndromes"])} for s in segs_h]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_ALU_TFLOPS,
+                     "traffic": measured_traffic(a.precision, a.count, a.workload),
                      "flops_per_launch": flops_per_step, "kernel": "fwd_kernel"},
         "wall_s": wall,
     }

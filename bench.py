@@ -10,7 +10,12 @@ timed once beside it, and both are compared with the FP64 form on a sample.
 Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--precision bf16|fp32plain|fp32|fp64]
-                  [--compare fp32plain] [--workload c3|c4] [--cpu-seconds S] [--no-cpu]
+                  [--compare fp32plain] [--workload c3|c4|c5] [--cpu-seconds S] [--no-cpu]
+
+--workload c4 decodes the mixed batch (distances 5..15) in one launch;
+--workload c5 times the adjoint (forward + backward) on the gradient workload
+(d = 11, per-qubit log-uniform rates, 8,192 syndromes, chi = 24, FP32 unless
+--precision says otherwise).
 """
 import argparse
 import json
@@ -36,7 +41,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16")
     ap.add_argument("--compare", default="fp32plain", help="second form timed once ('' to skip)")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"])
     ap.add_argument("--count", type=int, default=COUNT)
     ap.add_argument("--fp64-sample", type=int, default=512, help="syndromes decoded in FP64 for the error report")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -105,6 +110,56 @@ def measured_traffic(precision, count, workload):
     return None
 
 
+def bench_adjoint(a, torch, tn, synth, dev, stream):
+    """Forward + backward of sum_b log P(s_b) over the gradient workload."""
+    s = synth.config_inputs("C5")[0]
+    prec = a.precision if a.precision != "bf16" else "fp32"
+    n = len(s["syndromes"])
+    seg = tn.SegmentInput(s["d"], s["chi"], torch.from_numpy(s["syndromes"]).to(dev),
+                          torch.from_numpy(s["rates"]).to(dev), None, prec)
+    gw = torch.ones(n, dtype=torch.float64, device=dev)
+    fwd_flops = 4.0 * n * tn.plan_info(s["d"], s["chi"], prec)["flops"]
+    print("bench: adjoint d=%d chi=%d %s, %d syndromes" % (s["d"], s["chi"], prec, n), file=sys.stderr, flush=True)
+    for _ in range(a.warmup):
+        tn.coset_loglik_backward([seg], [gw])
+    torch.cuda.synchronize()
+    ev = []
+    for i in range(a.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        _, grads = tn.coset_loglik_backward([seg], [gw])
+        e1.record(stream)
+        ev.append((e0, e1))
+    torch.cuda.synchronize()
+    ms_step = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    tn.decode_segments([seg])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_fwd = e0.elapsed_time(e1)
+    # counted work of the backward: forward sweep with checkpoints, recompute of
+    # every segment, transposed bottom-up sweep (three forward sweeps' worth of
+    # row steps) plus the forward pass that supplies log Z; environments excluded
+    flops = 4.0 * fwd_flops
+    achieved = flops / (ms_step / 1e3) / 1e12
+    g = grads[0].cpu().numpy()
+    out = {
+        "metric": "syndromes/s of the adjoint d sum log P(s) / d ln p at d=11 chi=24 (gradient workload)",
+        "value": n / (ms_step / 1e3), "unit": "syndromes/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[prec], "data": "synthetic",
+        "config": {"workload": "d=11, per-qubit log-uniform rates in [1e-3, 5e-2], %d syndromes, chi=24" % n,
+                   "precision": prec, "parameters": int(g.size)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None, "flops_per_launch": flops,
+                     "kernel": "bwd_kernel (+ fwd_kernel)"},
+        "forward_only": {"ms": ms_fwd, "value": n / (ms_fwd / 1e3), "backward_over_forward": ms_step / ms_fwd},
+        "grad_abs_sum": float(np.abs(g).sum()),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -121,6 +176,9 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    if a.workload == "c5":
+        bench_adjoint(a, torch, tn, synth, dev, stream)
+        return
     if a.workload == "c3":
         rates = synth.depolarizing(D, P)
         smp = synth.sample(D, rates, a.count, SEED)

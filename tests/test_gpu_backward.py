@@ -195,3 +195,26 @@ def test_score_identity():
     tot = np.array(tot)
     mean, sd = tot.mean(0), tot.std(0, ddof=1)
     assert np.all(np.abs(mean) < 5 * sd / np.sqrt(nb) + 1e-9)
+
+
+@pytest.mark.slow
+def test_c5_gradient_full_batch():
+    """The gradient workload (d = 11, per-qubit log-uniform rates, chi = 24):
+    the FP32 adjoint over all 8,192 syndromes against the FP64 adjoint, and the
+    FP64 adjoint against FP64 central differences (step 1e-4 in ln p) on 32
+    random parameters over a 512-syndrome share."""
+    s = synth.config_inputs("C5")[0]
+    d, chi = s["d"], s["chi"]
+    syn = s["syndromes"]
+    rates = s["rates"][0] if s["rates"].ndim == 3 else s["rates"]  # one model
+    n = len(syn)
+    g32, _, _ = gpu_grad(d, chi, syn, rates, "fp32", np.ones(n))
+    g64, _, _ = gpu_grad(d, chi, syn, rates, "fp64", np.ones(n))
+    assert rel_err(g32, g64) < 1e-3
+    sub = syn[:512]
+    gs, _, _ = gpu_grad(d, chi, sub, rates, "fp64", np.ones(512))
+    rng = np.random.default_rng(5)
+    coords = [(int(q), int(k)) for q, k in zip(rng.integers(0, d * d, 32), rng.integers(0, 3, 32))]
+    fd = gpu_fd(d, chi, sub, rates, "fp64", np.ones(512), coords)
+    sel = np.array([gs[q, k] for q, k in coords])
+    assert np.max(np.abs(sel - fd)) < 1e-4 * np.max(np.abs(gs))

@@ -212,3 +212,21 @@ def test_deterministic_and_segment_independent(dev):
     for (d, chi, syn, r), x in zip(ins, a):
         single, _, _ = run(dev, d, chi, "fp32", syn, r)
         assert np.array_equal(single, x)
+
+
+def test_c2_sweep_fp32plain_vs_exact(dev):
+    """The d = 9 p-sweep (chi = 16, plain FP32): the first 512 syndromes of
+    every p against the exact oracle.  Truncation at chi = 16 is not exact at
+    d = 9, so the check is on log P(s) and on classes away from ties."""
+    segs = synth.config_inputs("C2", scale=512 / 65536)
+    ins = [tn.SegmentInput(s["d"], s["chi"], torch.from_numpy(s["syndromes"]).to(dev),
+                           torch.from_numpy(s["rates"]).to(dev), None, "fp32plain") for s in segs]
+    outs = tn.decode_segments(ins)
+    for s, o in zip(segs, outs):
+        ref = oracle.transfer(s["d"], s["rates"], s["syndromes"], threads=8)
+        lp_ref, _ = oracle.decide(ref)
+        lp = o.logp.cpu().numpy()
+        err = float(np.max(np.abs(lp - lp_ref)))
+        print("C2 p=%.2f max |dlogP| vs exact = %.3g" % (s["p"], err))
+        assert err < 1e-2
+        check_classes(o.cls.cpu().numpy(), ref, 1e-2)

@@ -5,7 +5,7 @@
  * The problem (paper Sec. 2.3, eqs. "coset_prob" and "mld_formal"): for a
  * syndrome s of the [[d^2, 1, d]] rotated surface code under independent
  * per-qubit Pauli noise with probability vectors (p_I, p_X, p_Y, p_Z)_q
- * (Sec. 3.1.1), compute the four coset partition functions
+ * (Sec. 2.2), compute the four coset partition functions
  *     Z_l(s) = sum of Pr(E) over errors E with syndrome s and logical class l,
  * l in {I, X, Y, Z}, the posterior log P(l|s) and the maximum-likelihood class.
  * Z_l is contracted as the generator-picture tensor network of Sec. 3.2.1 by
@@ -56,10 +56,13 @@ typedef enum {
   TN_FP64 = 0,       /* every step in FP64 */
   TN_FP32 = 1,       /* MPS and MPO.MPS contractions in FP32; the LQ and SVD
                         factorisations of the truncation in FP64 */
-  TN_BF16 = 2,       /* MPS and MPO.MPS contractions in bf16 on MFMA with FP32
-                        accumulation; factorisations in FP64 */
-  TN_FP32_PLAIN = 3  /* every contraction and factorisation in FP32 (reductions
-                        accumulate in FP64); the plain single-precision form */
+  TN_BF16 = 2,       /* MPS stored in FP32; the two contraction GEMMs of each
+                        site step (MPO.MPS times the carried factor, carry times
+                        Q) on bf16 MFMA with FP32 accumulation, operands split
+                        into bf16 high and low parts; factorisations in FP32 */
+  TN_FP32_PLAIN = 3  /* every contraction and factorisation in FP32 (norms and
+                        Jacobi inner products accumulate in FP64); the plain
+                        single-precision form */
 } tn_precision;
 /* Log-scales, log Z, log P(s) and the class decision are FP64 in every form. */
 

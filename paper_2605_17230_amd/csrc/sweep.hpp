@@ -312,7 +312,11 @@ __device__ void lq_form_q(Real* X, int m, int n, int ld, const Real* tau, Real* 
 
 // Register-resident Householder LQ for m <= 64 rows and n <= 256 columns:
 // lane group g (16 lanes) keeps rows g and g + 32 in registers, lane l holds
-// columns l + 16 c.  Same arithmetic and output layout as lq_factor; only the
+// columns l + 16 c.  Same reflectors and output layout as lq_factor, except
+// that the dot products of the row updates accumulate in the factorisation
+// type (FP32 in the FP32 forms: the reflector's leading entry is 1, so the
+// dot keeps the scale of the row's own entry and only terms far below it can
+// underflow); row norms stay FP64.  Only the
 // reflector of each step goes through LDS (staged with explicit zeros and the
 // implicit one in vb + (i & 1) * n, so the row update is branch-free).  The
 // owner of row i + 1 builds the next reflector as soon as it has updated that
@@ -320,17 +324,19 @@ __device__ void lq_form_q(Real* X, int m, int n, int ld, const Real* tau, Real* 
 constexpr int LQR_RPG = 2, LQR_NPL = 16;
 __device__ inline bool lq_regs_fit(int m, int n) { return m <= LQR_RPG * (NT / 16) && n <= LQR_NPL * 16; }
 
-template <typename Real>
+// NPL: columns per lane held in registers (n <= 16 NPL); instantiated for 8
+// and 16 so that 128-column matrices do not run 256-column loops.
+template <typename Real, int NPL = LQR_NPL>
 __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* diag, double* red, Real* vb) {
   const int k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
   constexpr int NG = NT / 16;
-  Real x[LQR_RPG][LQR_NPL];
+  Real x[LQR_RPG][NPL];
 #pragma unroll
   for (int j = 0; j < LQR_RPG; ++j) {
     const int r = grp + NG * j;
 #pragma unroll
-    for (int c = 0; c < LQR_NPL; ++c) {
+    for (int c = 0; c < NPL; ++c) {
       const int col = lane + 16 * c;
       x[j][c] = (r < m && col < n) ? X[r * ld + col] : Real(0);
     }
@@ -339,7 +345,7 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
   auto reflector = [&](int i, Real* xr) {
     double tp[4] = {0.0, 0.0, 0.0, 0.0}, x0 = 0.0;  // four partial sums: short FMA chains
 #pragma unroll
-    for (int c = 0; c < LQR_NPL; ++c) {
+    for (int c = 0; c < NPL; ++c) {
       const int col = lane + 16 * c;
       if (col > i) tp[c & 3] += (double)xr[c] * (double)xr[c];
       if (col == i) x0 = (double)xr[c];
@@ -356,7 +362,7 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
     }
     Real* v = vb + (i & 1) * n;
 #pragma unroll
-    for (int c = 0; c < LQR_NPL; ++c) {
+    for (int c = 0; c < NPL; ++c) {
       const int col = lane + 16 * c;
       if (live && col > i) xr[c] = Real((double)xr[c] * scale);
       if (col < n) v[col] = col < i ? Real(0) : (col == i ? Real(1) : xr[c]);
@@ -372,9 +378,9 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
   for (int i = 0; i < k; ++i) {
     const double t = red[i & 1];
     const Real* v = vb + (i & 1) * n;
-    Real vv[LQR_NPL];
+    Real vv[NPL];
 #pragma unroll
-    for (int c = 0; c < LQR_NPL; ++c) {
+    for (int c = 0; c < NPL; ++c) {
       const int col = lane + 16 * c;
       vv[c] = col < n ? v[col] : Real(0);
     }
@@ -383,13 +389,13 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
       const int r = grp + NG * j;
       if (r > i && r < m) {
         if (t != 0.0) {
-          double dp[4] = {0.0, 0.0, 0.0, 0.0};
+          Real dp[4] = {Real(0), Real(0), Real(0), Real(0)};
 #pragma unroll
-          for (int c = 0; c < LQR_NPL; ++c) dp[c & 3] += (double)x[j][c] * (double)vv[c];
-          const double dot = group_sum((dp[0] + dp[1]) + (dp[2] + dp[3]), 16);
+          for (int c = 0; c < NPL; ++c) dp[c & 3] += x[j][c] * vv[c];
+          const double dot = (double)group_sum((dp[0] + dp[1]) + (dp[2] + dp[3]), 16);
           const Real w = Real(dot * t);
 #pragma unroll
-          for (int c = 0; c < LQR_NPL; ++c) x[j][c] -= w * vv[c];
+          for (int c = 0; c < NPL; ++c) x[j][c] -= w * vv[c];
         }
         if (r == i + 1 && r < k) reflector(r, x[j]);
       }
@@ -400,7 +406,7 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
   for (int j = 0; j < LQR_RPG; ++j) {
     const int r = grp + NG * j;
 #pragma unroll
-    for (int c = 0; c < LQR_NPL; ++c) {
+    for (int c = 0; c < NPL; ++c) {
       const int col = lane + 16 * c;
       if (r < m && col < n) X[r * ld + col] = x[j][c];
     }
@@ -413,12 +419,12 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
 // H_{r-1}, ..., H_0, which involves no other row of Q, so each lane group
 // builds its rows (r and 2*32-1-r, balancing the step counts) with no barrier,
 // reading the reflectors from X.  One barrier before the rows are stored.
-template <typename Real>
+template <typename Real, int NPL = LQR_NPL>
 __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
   const int k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
   constexpr int NG = NT / 16;
-  Real q[LQR_RPG][LQR_NPL];
+  Real q[LQR_RPG][NPL];
 #pragma unroll
   for (int j = 0; j < LQR_RPG; ++j) {
     const int r = j == 0 ? grp : 2 * NG - 1 - grp;
@@ -427,7 +433,7 @@ __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
       const Real t = tau[r];
       const Real* xr = X + r * ld;
 #pragma unroll
-      for (int c = 0; c < LQR_NPL; ++c) {
+      for (int c = 0; c < NPL; ++c) {
         const int col = lane + 16 * c;
         const Real vc = col < r ? Real(0) : (col == r ? Real(1) : (col < n ? xr[col] : Real(0)));
         q[j][c] = (col == r ? Real(1) : Real(0)) - t * vc;
@@ -437,18 +443,18 @@ __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
       const Real t = tau[i];
       if (t == Real(0)) continue;
       const Real* xi = X + i * ld;
-      Real vv[LQR_NPL];
-      double dp[4] = {0.0, 0.0, 0.0, 0.0};
+      Real vv[NPL];
+      Real dp[4] = {Real(0), Real(0), Real(0), Real(0)};
 #pragma unroll
-      for (int c = 0; c < LQR_NPL; ++c) {
+      for (int c = 0; c < NPL; ++c) {
         const int col = lane + 16 * c;
         vv[c] = col < i ? Real(0) : (col == i ? Real(1) : (col < n ? xi[col] : Real(0)));
-        dp[c & 3] += (double)q[j][c] * (double)vv[c];
+        dp[c & 3] += q[j][c] * vv[c];
       }
-      const double dot = group_sum((dp[0] + dp[1]) + (dp[2] + dp[3]), 16);
+      const Real dot = group_sum((dp[0] + dp[1]) + (dp[2] + dp[3]), 16);
       const Real w = Real(dot) * t;
 #pragma unroll
-      for (int c = 0; c < LQR_NPL; ++c) q[j][c] -= w * vv[c];
+      for (int c = 0; c < NPL; ++c) q[j][c] -= w * vv[c];
     }
   }
   __syncthreads();
@@ -457,7 +463,7 @@ __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
     const int r = j == 0 ? grp : 2 * NG - 1 - grp;
     if (r >= k) continue;
 #pragma unroll
-    for (int c = 0; c < LQR_NPL; ++c) {
+    for (int c = 0; c < NPL; ++c) {
       const int col = lane + 16 * c;
       if (col < n) X[r * ld + col] = q[j][c];
     }
@@ -468,13 +474,21 @@ __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
 // Dispatch: registers when the matrix fits, else the LDS-resident version.
 template <typename Real>
 __device__ inline void lq_factor_any(Real* X, int m, int n, int ld, Real* tau, Real* diag, double* red, Real* vb) {
-  if (lq_regs_fit(m, n)) lq_factor_regs<Real>(X, m, n, ld, tau, diag, red, vb);
-  else lq_factor<Real>(X, m, n, ld, tau, diag, red);
+  if (lq_regs_fit(m, n)) {
+    if (n <= 128) lq_factor_regs<Real, 8>(X, m, n, ld, tau, diag, red, vb);
+    else lq_factor_regs<Real, 16>(X, m, n, ld, tau, diag, red, vb);
+  } else {
+    lq_factor<Real>(X, m, n, ld, tau, diag, red);
+  }
 }
 template <typename Real>
 __device__ inline void lq_form_q_any(Real* X, int m, int n, int ld, const Real* tau, Real* v) {
-  if (lq_regs_fit(m, n)) lq_form_q_regs<Real>(X, m, n, ld, tau);
-  else lq_form_q<Real>(X, m, n, ld, tau, v);
+  if (lq_regs_fit(m, n)) {
+    if (n <= 128) lq_form_q_regs<Real, 8>(X, m, n, ld, tau);
+    else lq_form_q_regs<Real, 16>(X, m, n, ld, tau);
+  } else {
+    lq_form_q<Real>(X, m, n, ld, tau, v);
+  }
 }
 
 // One-sided (Hestenes) Jacobi on the columns of M (rows x cols, column-major,

@@ -15,6 +15,8 @@ qubits at any d):
     oracle's top classes;
   * truncated runs: the stated truncation error bound and class agreement.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -230,3 +232,29 @@ def test_c2_sweep_fp32plain_vs_exact(dev):
         print("C2 p=%.2f max |dlogP| vs exact = %.3g" % (s["p"], err))
         assert err < 1e-2
         check_classes(o.cls.cpu().numpy(), ref, 1e-2)
+
+
+GOLDEN_C3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_oracle_logz.txt")
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["bf16", "fp32plain"])
+def test_c3_full_batch_vs_exact(dev, prec):
+    """The benchmark's launch (d = 17, chi = 32, all 16,384 syndromes in one
+    call) against the exact oracle values of its first 1,024 syndromes
+    (tests/golden/c3_oracle_logz.txt, written by make_c3_oracle.py from the
+    oracle alone): classes agree on >= 99.9 %, and wherever the oracle's top-two
+    gap exceeds the stated error bound; log P(s) within 1e-2."""
+    ref = np.loadtxt(GOLDEN_C3)
+    r = synth.depolarizing(17, 0.12)
+    smp = synth.sample(17, r, 16384, seed=3000)
+    logz, logp, cls = run(dev, 17, 32, prec, smp["syndromes"], r)
+    n = len(ref)
+    lp_ref, cls_ref = oracle.decide(ref)
+    err_lp = float(np.max(np.abs(logp[:n] - lp_ref)))
+    agree = float((cls[:n] == cls_ref).mean())
+    print("C3 %s: max |dlogP| %.3g, class agreement %.5f over %d" % (prec, err_lp, agree, n))
+    assert err_lp < 1e-2
+    assert agree >= 0.999
+    check_classes(cls[:n], ref, 0.05)
+    assert np.all(np.isfinite(logp))

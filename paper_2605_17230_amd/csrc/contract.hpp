@@ -209,14 +209,14 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
       __syncthreads();
       for (int so = 0; so < qo; ++so) {
         // T[(l,a)][(r,b)] = sum_si Aj[l][si][r] W[a][si][so][b]
-        for (int e = tid; e < mJ * RB; e += NT) {
-          const int la = e / RB, rb = e % RB;
-          const int l = la / A, a = la % A, r = rb / B, bb = rb % B;
+        // (A and B, the MPO bonds, are 1 or 2)
+        for_2d(mJ, RB, [&](int la, int rb) {
+          const int l = A == 2 ? la >> 1 : la, a = la & (A - 1), r = B == 2 ? rb >> 1 : rb, bb = rb & (B - 1);
           Real acc = 0;
           for (int si = 0; si < qi; ++si)
             acc += Aj[(l * qi + si) * Dr + r] * Wv[((a * qi + si) * qo + so) * B + bb];
-          T[e] = acc;
-        }
+          T[la * RB + rb] = acc;
+        });
         __syncthreads();
         // X[:, so*kr + c] = T . L
         contract_gemm<GM, Real>(mJ, kr, RB, T, RB, L, kr, 0, 0,
@@ -225,10 +225,7 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
       }
       lq_factor_any<Fac>(X, mJ, nn, nn, tau, diag, dred, vtmp);
       // L (mJ x k) for the site to the left
-      for (int e = tid; e < mJ * k; e += NT) {
-        const int r = e / k, c = e % k;
-        L[e] = Real(c < r ? X[r * nn + c] : (c == r ? diag[r] : Fac(0)));
-      }
+      for_2d(mJ, k, [&](int r, int c) { L[r * k + c] = Real(c < r ? X[r * nn + c] : (c == r ? diag[r] : Fac(0))); });
       __syncthreads();
       lq_form_q_any<Fac>(X, mJ, nn, nn, tau, vtmp);
       for (int e = tid; e < k * nn; e += NT) g[e] = Real(X[e]);
@@ -259,29 +256,24 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
       // M[(l,so)][c] = sum_k C[l][k] Q[k][so][c] (Q read from the site region),
       // stored as M^T rows: Mm[c*ldm + (l,so)]
       contract_gemm<GM, Real>(Dl, nn, k, C, k, g, nn, 0, 0, [&](int i, int j, Real v) {
-        const int so = j / kr, c = j % kr;
+        int so = 0, c = j;  // j = so * kr + c with so < qo <= 4
+        while (c >= kr) {
+          c -= kr;
+          ++so;
+        }
         Mm[c * ldm + i * qo + so] = Fac(v);
       });
       __syncthreads();
       // M^T = Lf Qf (LQ), i.e. M = Qf^T Lf^T: a QR factorisation of M
       lq_factor_any<Fac>(Mm, kr, R, ldm, tau, diag, dred, vtmp);
       // Lf (kr x k2) -> Lt, column-major (column j at Lt + j*ldl)
-      for (int e = tid; e < kr * k2; e += NT) {
-        const int r = e / k2, c = e % k2;
-        Lt[c * ldl + r] = c < r ? Mm[r * ldm + c] : (c == r ? diag[r] : Fac(0));
-      }
+      for_2d(kr, k2, [&](int r, int c) { Lt[c * ldl + r] = c < r ? Mm[r * ldm + c] : (c == r ? diag[r] : Fac(0)); });
       __syncthreads();
       lq_form_q_any<Fac>(Mm, kr, R, ldm, tau, vtmp);  // rows 0..k2-1 of Mm: Qf (k2 x R)
       if (!cut) {
         // A[(l,so)][r] = Qf[r][(l,so)], carry C[r][c] = Lf[c][r]
-        for (int e = tid; e < R * Dn; e += NT) {
-          const int lso = e / Dn, r = e % Dn;
-          g[e] = Real(Mm[r * ldm + lso]);
-        }
-        for (int e = tid; e < Dn * kr; e += NT) {
-          const int r = e / kr, c = e % kr;
-          C[e] = Real(Lt[r * ldl + c]);
-        }
+        for_2d(R, Dn, [&](int lso, int r) { g[lso * Dn + r] = Real(Mm[r * ldm + lso]); });
+        for_2d(Dn, kr, [&](int r, int c) { C[r * kr + c] = Real(Lt[r * ldl + c]); });
         __syncthreads();
         if (J == nsite - 1) {
           // last site: 1x1 carry = remaining norm (sign folded into the site)
@@ -298,7 +290,7 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
       } else {
         // one-sided Jacobi on the columns of Lf: Lf W = U' S, so that
         // M = (Qf^T W) S U'^T; keep the Dn largest singular values
-        for (int e = tid; e < k2 * k2; e += NT) Vv[(e / k2) * ldl + (e % k2)] = (e / k2 == e % k2) ? Fac(1) : Fac(0);
+        for_2d(k2, k2, [&](int r, int c) { Vv[r * ldl + c] = r == c ? Fac(1) : Fac(0); });
         __syncthreads();
         jacobi_svd<Fac>(Lt, kr, k2, ldl, Vv, ldl, SplitTol<Fac>::v, w.s_flag, dred, w.nrm);
         for (int c = tid; c < k2; c += NT) {
@@ -318,17 +310,13 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
         }
         __syncthreads();
         // A[(l,so)][r] = sum_c Qf[c][(l,so)] W[c][perm r];  C[r][c'] = (Lf W)[c'][perm r]
-        for (int e = tid; e < R * Dn; e += NT) {
-          const int lso = e / Dn, r = e % Dn;
+        for_2d(R, Dn, [&](int lso, int r) {
           const Fac* w = Vv + perm[r] * ldl;
           Fac acc = 0;
           for (int c = 0; c < k2; ++c) acc += Mm[c * ldm + lso] * w[c];
-          g[e] = Real(acc);
-        }
-        for (int e = tid; e < Dn * kr; e += NT) {
-          const int r = e / kr, c = e % kr;
-          C[e] = Real(Lt[perm[r] * ldl + c]);
-        }
+          g[lso * Dn + r] = Real(acc);
+        });
+        for_2d(Dn, kr, [&](int r, int c) { C[r * kr + c] = Real(Lt[perm[r] * ldl + c]); });
         __syncthreads();
       }
       if (w.s_dead[0]) break;

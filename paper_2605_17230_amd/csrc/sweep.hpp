@@ -104,6 +104,24 @@ __device__ inline Real block_sum(Real v, Real* red) {
   return s;
 }
 
+// Visit every (i, j) of an R x C index space; element i*C + j goes to thread
+// (i*C + j) mod NT, as in a flat loop, but without a division per element.
+template <typename F>
+__device__ inline void for_2d(int R, int C, F f) {
+  if (R <= 0 || C <= 0) return;
+  const int di = NT / C, dj = NT - di * C;
+  int i = (int)threadIdx.x / C, j = (int)threadIdx.x - i * C;
+  while (i < R) {
+    f(i, j);
+    i += di;
+    j += dj;
+    if (j >= C) {
+      j -= C;
+      ++i;
+    }
+  }
+}
+
 // C = A (MxK, row-major lda) * B (KxN, row-major ldb); store(i, j, value).
 // 4x4 register tiles; threads sweep tiles row-major.
 template <typename Real, typename Store>
@@ -542,19 +560,22 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
       if (c < cols && lane == 0) nrm[c] = sq;
     }
     __syncthreads();
+    // circle method: group g pairs (rd + g, rd - g) mod (N - 1), group 0 pairs
+    // (rd, N - 1); the two indices advance by one per round (no divisions)
+    int pp = g == 0 ? 0 : (g < N - 1 ? g : g % (N - 1));
+    int qq = g == 0 ? N - 1 : (N - 1 - pp == N - 1 ? 0 : N - 1 - pp);
     for (int rd = 0; rd < N - 1; ++rd) {
-      int p, q;
-      if (g == 0) {
-        p = rd;
-        q = N - 1;
-      } else {
-        p = (rd + g) % (N - 1);
-        q = (rd - g + N - 1) % (N - 1);
-      }
+      int p = pp, q = qq;
       if (p > q) {
         const int t = p;
         p = q;
         q = t;
+      }
+      if (g != 0) {
+        pp = pp + 1 == N - 1 ? 0 : pp + 1;
+        qq = qq + 1 == N - 1 ? 0 : qq + 1;
+      } else {
+        pp = pp + 1;
       }
       const bool act = g < P && q < cols;
       Real* a = M + (act ? p : 0) * ldm;

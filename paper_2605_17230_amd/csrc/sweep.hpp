@@ -514,34 +514,55 @@ __device__ inline void lq_form_q_any(Real* X, int m, int n, int ld, const Real* 
 // column-major, ldv), which must hold the identity on entry.  Afterwards the
 // columns of M are mutually orthogonal: M_in V = M_out, and the column norms
 // are the singular values.  Parallel cyclic ordering (circle method): each
-// round rotates cols'/2 disjoint pairs, one pair per group of G lanes, with
-// the pair's columns held in registers.
+// round rotates n'/2 disjoint pairs, one pair per group of G lanes, with the
+// pair's columns held in registers.
 //
-// A pair is left alone once its cosine is below tol, or once what a rotation
-// would remove is below the rounding level of the storage type: |a.b| <=
-// k eps max(|a|^2, |b|^2) (the component of the smaller column along the
-// larger one is noise of the larger), or |a.b| <= (k eps |M|_F)^2 (both
-// columns are noise of the matrix), with k = sqrt(rows).  Without the last
-// two tests, columns at the rounding floor of a strongly graded matrix keep
-// rotating forever.  The iteration stops after a sweep in which no rotated
-// pair had a cosine above sqrt(tol / cols): with quadratic convergence the
-// pairs are then below tol.  Returns the number of sweeps.
+// Columns whose norm is below k eps |M|_F (k = sqrt(rows)) are rounding noise
+// of the matrix: they are left out of the rotations altogether (they keep
+// their place and an identity column of V), so a graded matrix with n live
+// columns costs n - 1 rounds per sweep instead of cols - 1.  Among the live
+// columns a pair is left alone once its cosine is below tol, or once what a
+// rotation would remove is below the rounding level of the storage type:
+// |a.b| <= k eps max(|a|^2, |b|^2), or |a.b| <= (k eps |M|_F)^2.  Without
+// these tests, columns at the rounding floor keep rotating forever.  The
+// iteration stops after a sweep in which no rotated pair had a cosine above
+// sqrt(tol / cols): with quadratic convergence the pairs are then below tol.
+// lst: int scratch of cols entries.  Returns the number of sweeps.
 template <typename Real>
 __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv, double tol, int* flag,
-                          double* red, double* nrm) {
+                          double* red, double* nrm, int* lst) {
   constexpr int MAXR = 4;  // rows (and V rows) lane + j G, j < MAXR, live in registers; the rest stream from LDS
   if (cols < 2) return 0;
-  const int N = cols + (cols & 1);
+  const int tid = threadIdx.x;
+  (void)red;
+  // squared column norms, the Frobenius norm as their sum, and the live columns
+  for (int c = tid >> 4; c < cols; c += NT / 16) {
+    double sq = 0;
+    for (int r = tid & 15; r < rows; r += 16) sq += (double)M[c * ldm + r] * (double)M[c * ldm + r];
+    sq = group_sum(sq, 16);
+    if ((tid & 15) == 0) nrm[c] = sq;
+  }
+  __syncthreads();
+  double nf2 = 0;
+  for (int c = 0; c < cols; ++c) nf2 += nrm[c];  // same order in every thread
+  const double keps = sqrt((double)rows) * (double)Eps<Real>::v;
+  const double floor2 = keps * keps * nf2;
+  int nlive = 0;
+  for (int c = 0; c < cols; ++c) nlive += nrm[c] > floor2;
+  for (int c = tid; c < cols; c += NT) {
+    if (nrm[c] > floor2) {
+      int rank = 0;
+      for (int c2 = 0; c2 < c; ++c2) rank += nrm[c2] > floor2;
+      lst[rank] = c;
+    }
+  }
+  __syncthreads();
+  if (nlive < 2) return 1;
+  const int N = nlive + (nlive & 1);
   const int P = N >> 1;
   int G = WAVE;
   while (G > 1 && G * P > NT) G >>= 1;
-  const int tid = threadIdx.x, g = tid / G, lane = tid % G;
-  double part = 0;
-  for (int c = 0; c < cols; ++c)
-    for (int r = tid; r < rows; r += NT) part += (double)M[c * ldm + r] * (double)M[c * ldm + r];
-  const double nf2 = block_sum(part, red);
-  const double keps = sqrt((double)rows) * (double)Eps<Real>::v;
-  const double floor2 = keps * keps * nf2;
+  const int g = tid / G, lane = tid % G;
   const int nr = (rows + G - 1) / G, nc = (cols + G - 1) / G;
   // a sweep whose largest rotated cosine is below sqrt(tol / cols) leaves every
   // pair below tol (convergence is quadratic), so no confirming sweep follows
@@ -549,15 +570,18 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
   int sweep = 0;
   for (; sweep < 40; ++sweep) {
     if (tid == 0) *flag = 0;
-    // exact squared column norms at the start of every sweep; rotations then
-    // update them in closed form (|a'|^2 = |a|^2 - t a.b, |b'|^2 = |b|^2 + t a.b)
-    for (int c0 = 0; c0 < cols; c0 += NT / G) {
-      const int c = c0 + g;
-      double sq = 0;
-      if (c < cols)
-        for (int r = lane; r < rows; r += G) sq += (double)M[c * ldm + r] * (double)M[c * ldm + r];
-      sq = group_sum(sq, G);
-      if (c < cols && lane == 0) nrm[c] = sq;
+    if (sweep > 0) {
+      // exact squared norms of the live columns at the start of every sweep;
+      // rotations update them in closed form (|a'|^2 = |a|^2 - t a.b, |b'|^2 = |b|^2 + t a.b)
+      for (int i0 = 0; i0 < nlive; i0 += NT / G) {
+        const int i = i0 + g;
+        const int c = i < nlive ? lst[i] : 0;
+        double sq = 0;
+        if (i < nlive)
+          for (int r = lane; r < rows; r += G) sq += (double)M[c * ldm + r] * (double)M[c * ldm + r];
+        sq = group_sum(sq, G);
+        if (i < nlive && lane == 0) nrm[c] = sq;
+      }
     }
     __syncthreads();
     // circle method: group g pairs (rd + g, rd - g) mod (N - 1), group 0 pairs
@@ -577,9 +601,10 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
       } else {
         pp = pp + 1;
       }
-      const bool act = g < P && q < cols;
-      Real* a = M + (act ? p : 0) * ldm;
-      Real* b = M + (act ? q : 0) * ldm;
+      const bool act = g < P && q < nlive;
+      const int cp = act ? lst[p] : 0, cq = act ? lst[q] : 0;
+      Real* a = M + cp * ldm;
+      Real* b = M + cq * ldm;
       Real xa[MAXR], xb[MAXR];
       double gp[2] = {0.0, 0.0};  // FP64 sums: no underflow of small columns
 #pragma unroll
@@ -595,8 +620,8 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
       if (act)
         for (int r = lane + MAXR * G; r < rows; r += G) gp[0] += (double)a[r] * (double)b[r];
       // the rotation's V columns are loaded now so that their latency overlaps the reduction
-      Real* va = V + (act ? p : 0) * ldv;
-      Real* vb = V + (act ? q : 0) * ldv;
+      Real* va = V + cp * ldv;
+      Real* vb = V + cq * ldv;
       Real ya[MAXR], yb[MAXR];
 #pragma unroll
       for (int j = 0; j < MAXR; ++j) {
@@ -607,7 +632,7 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
           yb[j] = vb[r];
         }
       }
-      const double al = act ? nrm[p] : 0.0, be = act ? nrm[q] : 0.0;
+      const double al = act ? nrm[cp] : 0.0, be = act ? nrm[cq] : 0.0;
       const double ga = group_sum(gp[0] + gp[1], G);
       const double aga = fabs(ga);
       // squared form of |ga| > tol |a| |b| (the pair is far above the noise floor here)
@@ -662,8 +687,8 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
         }
         if (lane == 0) {
           if (ga * ga > big2 * al * be) *flag = 1;
-          nrm[p] = fmax(al - tn * ga, 0.0);
-          nrm[q] = fmax(be + tn * ga, 0.0);
+          nrm[cp] = fmax(al - tn * ga, 0.0);
+          nrm[cq] = fmax(be + tn * ga, 0.0);
         }
       }
       __syncthreads();

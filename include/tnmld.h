@@ -114,13 +114,17 @@ int tn_decode_batch(const tn_segment* segs, int32_t nseg, double tie_tol, void* 
  * from the bottom, and contracts the environment of every qubit tensor.
  * grad_logp[s]: device [count] of segment s; grad_log_rates[s]: device
  * [n_models][d*d][3], ACCUMULATED (+=) in FP64 by a deterministic reduction.
- * Also writes out_logz / out_logp of each segment (out_logp must be non-NULL).
+ * forward_done = 0: the call first runs the forward pass and writes out_logz /
+ * out_logp of each segment (out_logp must be non-NULL).  forward_done = 1:
+ * out_logz / out_logp already hold the forward results for exactly these
+ * inputs (e.g. from tn_decode_batch); they are read, not recomputed.
  * All segments of one call share one precision (else TN_EUNSUPPORTED).  Each
  * work-group walks a fixed stride of items, so the result is bitwise
  * reproducible for a given device and launch shape.
  * workspace: ws_bytes >= tn_workspace_size(segs, nseg, 1). */
 int tn_coset_loglik_backward(const tn_segment* segs, int32_t nseg, const double* const* grad_logp,
-                             double* const* grad_log_rates, void* workspace, size_t ws_bytes, void* stream);
+                             double* const* grad_log_rates, int32_t forward_done, void* workspace, size_t ws_bytes,
+                             void* stream);
 
 /* HOST helper: check layout of distance d.  type_out: host [d*d-1] (0 = X-type,
  * 1 = Z-type); support_out: host [d*d-1][4] qubit indices, -1 padded.

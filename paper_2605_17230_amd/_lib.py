@@ -53,7 +53,7 @@ def lib():
         L.tn_decode_batch.restype = ctypes.c_int
         L.tn_decode_batch.argtypes = [seg_p, I32, D, P, SZ, P]
         L.tn_coset_loglik_backward.restype = ctypes.c_int
-        L.tn_coset_loglik_backward.argtypes = [seg_p, I32, ctypes.POINTER(P), ctypes.POINTER(P), P, SZ, P]
+        L.tn_coset_loglik_backward.argtypes = [seg_p, I32, ctypes.POINTER(P), ctypes.POINTER(P), I32, P, SZ, P]
         L.tn_code_stabilizers.restype = ctypes.c_int
         L.tn_code_stabilizers.argtypes = [I32, P, P]
         L.tn_plan_info.restype = ctypes.c_int

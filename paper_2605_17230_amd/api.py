@@ -119,13 +119,27 @@ def coset_loglik(syndromes, rates, d, chi, precision="fp32", model_index=None):
     return outs[0].logz, outs[0].logp
 
 
-def coset_loglik_backward(segs, grad_logp, stream=None):
+def coset_loglik_backward(segs, grad_logp, stream=None, outputs=None):
     """d (sum_b grad_logp[b] log P(s_b)) / d ln rates for each segment.
 
-    grad_logp: list of float64 [B] device tensors, one per segment.  Returns
+    grad_logp: list of float64 [B] device tensors, one per segment.  outputs:
+    the SegmentOutput list of an earlier decode of exactly these inputs, whose
+    log Z / log P(s) are then reused instead of recomputed.  Returns
     (outputs, grads) with grads[i] float64 [M, d*d, 3] (a fresh zeroed tensor
     that the library accumulates into)."""
     arr, outs, keep = _prepare(segs)
+    forward_done = 0
+    if outputs is not None:
+        if len(outputs) != len(segs):
+            raise ValueError("one output per segment")
+        for i, o in enumerate(outputs):
+            if o.logz.shape != outs[i].logz.shape or o.logp.shape != outs[i].logp.shape:
+                raise ValueError("outputs do not match the segments")
+            arr[i].out_logz = o.logz.data_ptr()
+            arr[i].out_logp = o.logp.data_ptr()
+            arr[i].out_class = o.cls.data_ptr()
+        outs = list(outputs)
+        forward_done = 1
     L = lib()
     nbytes = L.tn_workspace_size(arr, len(segs), 1)
     if nbytes == 0:
@@ -142,8 +156,8 @@ def coset_loglik_backward(segs, grad_logp, stream=None):
     gp_arr = (ctypes.c_void_p * len(segs))(*[g.data_ptr() for g in gp])
     gr_arr = (ctypes.c_void_p * len(segs))(*[g.data_ptr() for g in grads])
     st = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
-    check(L.tn_coset_loglik_backward(arr, len(segs), gp_arr, gr_arr, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
-                                     ctypes.c_void_p(st)))
+    check(L.tn_coset_loglik_backward(arr, len(segs), gp_arr, gr_arr, forward_done, ctypes.c_void_p(ws.data_ptr()),
+                                     ws.numel(), ctypes.c_void_p(st)))
     del keep
     return outs, grads
 
@@ -158,6 +172,7 @@ class _LogPosterior(torch.autograd.Function):
         seg = SegmentInput(d, chi, syndromes, rates, model_index, precision)
         o = decode_segments([seg])[0]
         ctx.seg = seg
+        ctx.out = o
         ctx.rates_dim = log_rates.dim()
         ctx.mark_non_differentiable(o.logz)
         return o.logp, o.logz
@@ -166,7 +181,7 @@ class _LogPosterior(torch.autograd.Function):
     def backward(ctx, g_logp, g_logz):
         if g_logz is not None and bool((g_logz != 0).any()):
             raise NotImplementedError("only log P(s) is differentiable")
-        _, grads = coset_loglik_backward([ctx.seg], [g_logp])
+        _, grads = coset_loglik_backward([ctx.seg], [g_logp], outputs=[ctx.out])
         g = grads[0] if ctx.rates_dim == 3 else grads[0][0]
         return g, None, None, None, None, None
 

@@ -556,7 +556,8 @@ int tn_decode_batch(const tn_segment* segs, int32_t nseg, double tie_tol, void* 
 }
 
 int tn_coset_loglik_backward(const tn_segment* segs, int32_t nseg, const double* const* grad_logp,
-                             double* const* grad_log_rates, void* workspace, size_t ws_bytes, void* stream) {
+                             double* const* grad_log_rates, int32_t forward_done, void* workspace, size_t ws_bytes,
+                             void* stream) {
   BwdLayout bl;
   int rc = plan_backward(segs, nseg, &bl);
   if (rc) return rc;
@@ -568,7 +569,7 @@ int tn_coset_loglik_backward(const tn_segment* segs, int32_t nseg, const double*
   if (!workspace || ws_bytes < bl.total) return fail(TN_EINVAL, "workspace too small: need " + std::to_string(bl.total));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   // forward pass: log Z and log P(s) (the coset weights of the backward)
-  if ((rc = tn_coset_loglik(segs, nseg, workspace, ws_bytes, stream))) return rc;
+  if (!forward_done && (rc = tn_coset_loglik(segs, nseg, workspace, ws_bytes, stream))) return rc;
   char* base = reinterpret_cast<char*>(workspace) + bl.fwd_bytes;
   double* partials = reinterpret_cast<double*>(base);
   char* scratch = base + align_up((size_t)bl.nwg * bl.part_stride * sizeof(double));

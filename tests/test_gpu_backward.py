@@ -218,3 +218,18 @@ def test_c5_gradient_full_batch():
     fd = gpu_fd(d, chi, sub, rates, "fp64", np.ones(512), coords)
     sel = np.array([gs[q, k] for q, k in coords])
     assert np.max(np.abs(sel - fd)) < 1e-4 * np.max(np.abs(gs))
+
+
+def test_backward_reuses_forward_outputs():
+    """Passing the outputs of an earlier decode skips the forward pass and
+    gives the same gradient, bit for bit."""
+    tn = _tn()
+    d, chi = 7, 12
+    rates = synth.biased(d, 0.1, 10.0)
+    smp = synth.sample(d, rates, 64, seed=31)
+    seg = _seg(d, chi, smp["syndromes"], rates, "fp32")
+    gw = torch.from_numpy(np.random.default_rng(3).normal(size=64)).to(DEV)
+    _, g_full = tn.coset_loglik_backward([seg], [gw])
+    outs = tn.decode_segments([seg])
+    _, g_reuse = tn.coset_loglik_backward([seg], [gw], outputs=outs)
+    assert torch.equal(g_full[0], g_reuse[0])

@@ -77,6 +77,8 @@ __device__ void row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
     }
     __syncthreads();
   };
+  // physical dimensions are 1, 2 or 4 and MPO bonds 1 or 2: index splits are shifts
+  auto lg = [](int x) { return x == 4 ? 2 : (x == 2 ? 1 : 0); };
   // --- left environments ---------------------------------------------------
   if (tid == 0) env[s_eoff[0]] = Real(1);
   __syncthreads();
@@ -89,32 +91,33 @@ __device__ void row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
     const Real* E = env + s_eoff[J];
     Real* En = env + s_eoff[J + 1];
     load_w(st);
+    const int lqi = lg(qi), lqo = lg(qo), lB = lg(B);
     // P1[a][lF][si][rA] = sum_lA E[lA][a][lF] A[lA][si][rA]
-    for (int e = tid; e < Aa * DlF * qi * DrA; e += NT) {
-      const int rA = e % DrA, si = (e / DrA) % qi, lF = (e / (DrA * qi)) % DlF, a = e / (DrA * qi * DlF);
+    for_2d(Aa * DlF * qi, DrA, [&](int row, int rA) {
+      const int si = row & (qi - 1), t = row >> lqi, a = t >= DlF ? 1 : 0, lF = t - a * DlF;
       Real acc = 0;
       for (int lA = 0; lA < DlA; ++lA) acc += E[(lA * Aa + a) * DlF + lF] * Aj[(lA * qi + si) * DrA + rA];
-      P1[e] = acc;
-    }
+      P1[row * DrA + rA] = acc;
+    });
     __syncthreads();
     // P2[lF][so][b][rA] = sum_{a,si} P1[a][lF][si][rA] W[a][si][so][b]
-    for (int e = tid; e < DlF * qo * B * DrA; e += NT) {
-      const int rA = e % DrA, b = (e / DrA) % B, so = (e / (DrA * B)) % qo, lF = e / (DrA * B * qo);
+    for_2d(DlF * qo * B, DrA, [&](int row, int rA) {
+      const int b = row & (B - 1), t = row >> lB, so = t & (qo - 1), lF = t >> lqo;
       Real acc = 0;
       for (int a = 0; a < Aa; ++a)
         for (int si = 0; si < qi; ++si)
           acc += P1[((a * DlF + lF) * qi + si) * DrA + rA] * Wv[((a * qi + si) * qo + so) * B + b];
-      P2[e] = acc;
-    }
+      P2[row * DrA + rA] = acc;
+    });
     __syncthreads();
     // En[rA][b][rF] = sum_{lF,so} P2[lF][so][b][rA] F[lF][so][rF]
-    for (int e = tid; e < DrA * B * DrF; e += NT) {
-      const int rF = e % DrF, b = (e / DrF) % B, rA = e / (DrF * B);
+    for_2d(DrA * B, DrF, [&](int row, int rF) {
+      const int b = row & (B - 1), rA = row >> lB;
       Real acc = 0;
       for (int lF = 0; lF < DlF; ++lF)
         for (int so = 0; so < qo; ++so) acc += P2[((lF * qo + so) * B + b) * DrA + rA] * Fj[(lF * qo + so) * DrF + rF];
-      En[e] = acc;
-    }
+      En[row * DrF + rF] = acc;
+    });
     __syncthreads();
   }
   const double S = (double)env[s_eoff[nsite]];
@@ -132,27 +135,28 @@ __device__ void row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
     const Real* E = env + s_eoff[J];
     Real* Rn = env + s_roff[J];
     load_w(st);
+    const int lqi = lg(qi), lqo = lg(qo), lB = lg(B), lA_ = lg(Aa);
     // P1r[lF][so][rA][b] = sum_rF F[lF][so][rF] R[rA][b][rF]
-    for (int e = tid; e < DlF * qo * DrA * B; e += NT) {
-      const int b = e % B, rA = (e / B) % DrA, so = (e / (B * DrA)) % qo, lF = e / (B * DrA * qo);
+    for_2d(DlF * qo, DrA * B, [&](int row, int col) {
+      const int b = col & (B - 1), rA = col >> lB;
       Real acc = 0;
-      for (int rF = 0; rF < DrF; ++rF) acc += Fj[(lF * qo + so) * DrF + rF] * R[(rA * B + b) * DrF + rF];
-      P1[e] = acc;
-    }
+      for (int rF = 0; rF < DrF; ++rF) acc += Fj[row * DrF + rF] * R[(rA * B + b) * DrF + rF];
+      P1[row * (DrA * B) + col] = acc;
+    });
     __syncthreads();
     if (st.q >= 0) {
       // P3[a][lF][si][rA] = sum_lA E[lA][a][lF] A[lA][si][rA]
-      for (int e = tid; e < Aa * DlF * qi * DrA; e += NT) {
-        const int rA = e % DrA, si = (e / DrA) % qi, lF = (e / (DrA * qi)) % DlF, a = e / (DrA * qi * DlF);
+      for_2d(Aa * DlF * qi, DrA, [&](int row, int rA) {
+        const int si = row & (qi - 1), t = row >> lqi, a = t >= DlF ? 1 : 0, lF = t - a * DlF;
         Real acc = 0;
         for (int lA = 0; lA < DlA; ++lA) acc += E[(lA * Aa + a) * DlF + lF] * Aj[(lA * qi + si) * DrA + rA];
-        P3[e] = acc;
-      }
+        P3[row * DrA + rA] = acc;
+      });
       __syncthreads();
       // G[a][si][so][b] = sum_{lF,rA} P3[a][lF][si][rA] P1r[lF][so][rA][b], divided by the sandwich value
       const int ng = Aa * qi * qo * B;
       for (int e = tid; e < ng; e += NT) {
-        const int b = e % B, so = (e / B) % qo, si = (e / (B * qo)) % qi, a = e / (B * qo * qi);
+        const int b = e & (B - 1), so = (e >> lB) & (qo - 1), si = (e >> (lB + lqo)) & (qi - 1), a = e >> (lB + lqo + lqi);
         double acc = 0;
         for (int lF = 0; lF < DlF; ++lF)
           for (int rA = 0; rA < DrA; ++rA)
@@ -180,22 +184,22 @@ __device__ void row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
       __syncthreads();
     }
     // P2r[lF][si][a][rA] = sum_{so,b} P1r[lF][so][rA][b] W[a][si][so][b]
-    for (int e = tid; e < DlF * qi * Aa * DrA; e += NT) {
-      const int rA = e % DrA, a = (e / DrA) % Aa, si = (e / (DrA * Aa)) % qi, lF = e / (DrA * Aa * qi);
+    for_2d(DlF * qi * Aa, DrA, [&](int row, int rA) {
+      const int a = row & (Aa - 1), t = row >> lA_, si = t & (qi - 1), lF = t >> lqi;
       Real acc = 0;
       for (int so = 0; so < qo; ++so)
         for (int b = 0; b < B; ++b) acc += P1[((lF * qo + so) * DrA + rA) * B + b] * Wv[((a * qi + si) * qo + so) * B + b];
-      P2[e] = acc;
-    }
+      P2[row * DrA + rA] = acc;
+    });
     __syncthreads();
     // Rn[lA][a][lF] = sum_{si,rA} A[lA][si][rA] P2r[lF][si][a][rA]
-    for (int e = tid; e < DlA * Aa * DlF; e += NT) {
-      const int lF = e % DlF, a = (e / DlF) % Aa, lA = e / (DlF * Aa);
+    for_2d(DlA * Aa, DlF, [&](int row, int lF) {
+      const int a = row & (Aa - 1), lA = row >> lA_;
       Real acc = 0;
       for (int si = 0; si < qi; ++si)
         for (int rA = 0; rA < DrA; ++rA) acc += Aj[(lA * qi + si) * DrA + rA] * P2[((lF * qi + si) * Aa + a) * DrA + rA];
-      Rn[e] = acc;
-    }
+      Rn[row * DlF + lF] = acc;
+    });
     __syncthreads();
   }
 }

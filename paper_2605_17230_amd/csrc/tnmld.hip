@@ -8,9 +8,11 @@
 //   2. for each anti-diagonal row u of the 45-degree lattice: apply the row's
 //      MPO (bond 2, entries p_q(f_q xor P) resolved from codes) to the MPS,
 //      bring the product to right-canonical form by a right-to-left sweep of
-//      Householder LQ factorisations, then sweep left-to-right truncating every
-//      bond to chi by a one-sided Jacobi SVD (the paper's "successive SVD
-//      truncations"), and add the removed log-norm to an FP64 accumulator;
+//      Householder LQ factorisations, then sweep left-to-right with a QR of
+//      every site matrix, and on each bond that exceeds chi a one-sided Jacobi
+//      SVD of the triangular factor keeping the chi largest singular values
+//      (the paper's successive SVD truncations); the removed log-norms go to
+//      an FP64 accumulator;
 //   3. the last row leaves a product over columns that is summed out.
 #include <hip/hip_runtime.h>
 

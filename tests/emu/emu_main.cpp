@@ -1,0 +1,94 @@
+// Host entry points that run the device code of the sweep (forward and
+// adjoint) one (syndrome, coset) item at a time on NT host threads.  Test
+// infrastructure only: built by tests/test_kernel_emulation.py.
+#include "emu_hip.hpp"
+
+#include "adjoint.hpp"
+
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+using namespace tnmld;
+
+namespace {
+
+struct Barriers {
+  std::barrier<> block{NT};
+  std::vector<std::barrier<>*> own;
+  Barriers() {
+    g_block_bar = &block;
+    for (int w = 0; w < NT / 64; ++w) own.push_back(g_wave_bar[w] = new std::barrier<>(64));
+    for (int r = 0; r < NT / 16; ++r) own.push_back(g_row_bar[r] = new std::barrier<>(16));
+  }
+  ~Barriers() {
+    for (auto* b : own) delete b;
+  }
+};
+
+template <class F>
+void run_block(F f) {
+  std::vector<std::thread> th;
+  for (int t = 0; t < NT; ++t)
+    th.emplace_back([&, t] {
+      threadIdx.x = t;
+      f(t);
+    });
+  for (auto& x : th) x.join();
+}
+
+template <typename Real, typename Fac>
+int forward(int d, int chi, int group, const double* rates, const uint8_t* syn, int count, double* logz) {
+  Plan p;
+  if (!build_plan(d, chi, group, &p).empty()) return -1;
+  const LdsLayout lay = lds_layout(p.h, sizeof(Real), sizeof(Fac));
+  std::vector<double> smem(lay.bytes / 8 + 16), scr(p.h.scratch_elems * sizeof(Real) / 8 + 16);
+  JobDev job{p.blob.data(), rates, nullptr, syn, logz, nullptr, nullptr, count, 0, 0, 1, 0};
+  Barriers bars;
+  for (int b = 0; b < count; ++b)
+    for (int m = 0; m < 4; ++m)
+      run_block([&](int t) {
+        int label = 0;
+        const double lz = contract_one<Real, Fac>(job, b, m, (uint8_t*)smem.data(), lay, (Real*)scr.data(), &label);
+        if (t == 0) logz[b * 4 + label] = lz;
+      });
+  return 0;
+}
+
+template <typename Real, typename Fac>
+int gradient(int d, int chi, int group, const double* rates, const uint8_t* syn, int count, const double* logz,
+             const double* logp, const double* gradp, double* out) {
+  Plan p;
+  if (!build_plan(d, chi, group, &p).empty()) return -1;
+  const PlanHeader& H = p.h;
+  const LdsLayout lay = lds_layout(H, sizeof(Real), sizeof(Fac));
+  const int kseg = (int)std::ceil(std::sqrt((double)H.nstep));
+  const int ncp = (H.nstep + kseg - 1) / kseg;
+  const int64_t elems = 2 * H.scratch_elems + (int64_t)(ncp + kseg) * H.mps_elems + H.env_elems + 3 * H.tmp_elems;
+  std::vector<double> smem(lay.bytes / 8 + 16), scr(elems * sizeof(Real) / 8 + 16);
+  JobDev job{p.blob.data(), rates, nullptr, syn, const_cast<double*>(logz), logp, gradp, count, 0, 0, 1, 0};
+  Barriers bars;
+  for (int b = 0; b < count; ++b)
+    for (int m = 0; m < 4; ++m)
+      run_block([&](int) {
+        adjoint_one<Real, Fac, GEMM_VALU>(job, b, m, (uint8_t*)smem.data(), lay, (Real*)scr.data(), kseg, out);
+      });
+  return 0;
+}
+
+}  // namespace
+
+// precision: 0 = FP64, 1 = FP32 state with FP64 factorisations, 3 = plain FP32
+extern "C" int emu_forward(int d, int chi, int precision, int group, const double* rates, const uint8_t* syn,
+                           int count, double* logz) {
+  if (precision == 0) return forward<double, double>(d, chi, group, rates, syn, count, logz);
+  if (precision == 1) return forward<float, double>(d, chi, group, rates, syn, count, logz);
+  return forward<float, float>(d, chi, group, rates, syn, count, logz);
+}
+
+extern "C" int emu_gradient(int d, int chi, int precision, int group, const double* rates, const uint8_t* syn,
+                            int count, const double* logz, const double* logp, const double* gradp, double* out) {
+  if (precision == 0) return gradient<double, double>(d, chi, group, rates, syn, count, logz, logp, gradp, out);
+  if (precision == 1) return gradient<float, double>(d, chi, group, rates, syn, count, logz, logp, gradp, out);
+  return gradient<float, float>(d, chi, group, rates, syn, count, logz, logp, gradp, out);
+}

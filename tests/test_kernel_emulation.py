@@ -1,0 +1,79 @@
+"""The sweep kernels' own source, run on the host: tests/emu maps one
+work-group onto 512 std::threads (barriers for __syncthreads and the lane
+exchanges), so the forward contraction and the adjoint of
+paper_2605_17230_amd/csrc can be checked against the FP64 oracle without a
+GPU.  DPP lane moves are the one device feature replaced (by the same
+exchange through memory), so these tests pin the algorithm and its
+synchronisation, the GPU tests the lane layout."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+EMU = os.path.join(ROOT, "tests", "emu")
+CSRC = os.path.join(ROOT, "paper_2605_17230_amd", "csrc")
+LIB = os.path.join(EMU, "_build", "libemu.so")
+
+
+@pytest.fixture(scope="module")
+def emu():
+    os.makedirs(os.path.dirname(LIB), exist_ok=True)
+    subprocess.check_call(["g++", "-O2", "-std=c++20", "-shared", "-fPIC", "-I", CSRC, "-I", EMU,
+                           os.path.join(EMU, "emu_main.cpp"), os.path.join(CSRC, "plan.cpp"), "-o", LIB,
+                           "-lpthread"])
+    L = ctypes.CDLL(LIB)
+    P = ctypes.c_void_p
+    L.emu_forward.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_int, P]
+    L.emu_gradient.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_int, P, P, P, P]
+    return L
+
+
+def forward(L, d, chi, prec, group, rates, syn):
+    rates = np.ascontiguousarray(rates, np.float64)
+    syn = np.ascontiguousarray(syn, np.uint8)
+    out = np.full((len(syn), 4), np.nan)
+    assert L.emu_forward(d, chi, prec, group, rates.ctypes.data, syn.ctypes.data, len(syn), out.ctypes.data) == 0
+    return out
+
+
+@pytest.mark.parametrize("prec,group,tol", [(0, 1, 1e-12), (3, 2, 1e-4)])
+def test_d3_exact_forward(emu, prec, group, tol):
+    rates = synth.inhomogeneous(3, 0.01, 0.15, seed=1)
+    syn = synth.sample(3, rates, 1, seed=2)["syndromes"]
+    got = forward(emu, 3, 0, prec, group, rates, syn)
+    ref = oracle.transfer(3, rates, syn)
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(got), fin)
+    assert np.max(np.abs(got[fin] - ref[fin])) < tol
+
+
+def test_d3_truncated_forward_is_deterministic(emu):
+    """chi = 2 truncates every inner bond (Jacobi on every cut): two runs of
+    512 racing threads must agree bit for bit, and stay near the exact value."""
+    rates = synth.depolarizing(3, 0.1)
+    syn = synth.sample(3, rates, 1, seed=4)["syndromes"]
+    a = forward(emu, 3, 2, 0, 1, rates, syn)
+    b = forward(emu, 3, 2, 0, 1, rates, syn)
+    assert np.array_equal(a, b)
+    ref = oracle.transfer(3, rates, syn)
+    assert np.max(np.abs(np.logaddexp.reduce(a, 1) - np.logaddexp.reduce(ref, 1))) < 0.5
+
+
+def test_d3_gradient(emu):
+    rates = synth.inhomogeneous(3, 0.01, 0.15, seed=5)
+    syn = synth.sample(3, rates, 1, seed=6)["syndromes"]
+    logz = forward(emu, 3, 0, 0, 2, rates, syn)
+    logp = np.logaddexp.reduce(logz, 1)
+    gw = np.array([-0.7])
+    out = np.zeros((9, 3))
+    assert emu.emu_gradient(3, 0, 0, 2, np.ascontiguousarray(rates).ctypes.data,
+                            np.ascontiguousarray(syn, np.uint8).ctypes.data, len(syn), logz.ctypes.data,
+                            logp.ctypes.data, gw.ctypes.data, out.ctypes.data) == 0
+    ref = sum(w * oracle.grad_logp(3, rates, s)[0] for s, w in zip(syn, gw))
+    assert np.max(np.abs(out - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))

@@ -258,3 +258,61 @@ def test_c3_full_batch_vs_exact(dev, prec):
     assert agree >= 0.999
     check_classes(cls[:n], ref, 0.05)
     assert np.all(np.isfinite(logp))
+
+
+def brute_force_sparse(d, rates, syn):
+    """Exact log Z_l by enumerating every Pauli error on the qubits with
+    non-zero rates (all other qubits carry I with probability 1)."""
+    import itertools
+    n = d * d
+    support = [q for q in range(n) if rates[q].sum() > 0]
+    errs = np.zeros((4 ** len(support), n), np.uint8)
+    probs = np.ones(4 ** len(support))
+    for e, combo in enumerate(itertools.product(range(4), repeat=len(support))):
+        for q, pauli in zip(support, combo):
+            errs[e, q] = pauli
+            probs[e] *= (1.0 - rates[q].sum()) if pauli == 0 else rates[q, pauli - 1]
+    s_all = synth.syndromes_of(d, errs)
+    c_all = synth.classes_of(d, errs)
+    out = np.full((len(syn), 4), -np.inf)
+    for b, s in enumerate(syn):
+        hit = np.all(s_all == s, axis=1)
+        for cls in range(4):
+            z = probs[hit & (c_all == cls)].sum()
+            if z > 0:
+                out[b, cls] = np.log(z)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32plain", "bf16"])
+def test_largest_distance_sparse_support(dev, prec):
+    """d = 31 (the largest the library accepts) with noise on six qubits of a
+    3 x 3 patch: the bond dimension stays small, so chi = 4 is exact, and the
+    reference is a brute-force sum over the 4^6 errors on the support."""
+    d = 31
+    rates, syn = sparse_case(d, 6, seed=3)
+    ref = brute_force_sparse(d, rates, syn)
+    logz, _, cls = run(dev, d, 4, prec, syn, rates)
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(logz), fin)
+    err = float(np.max(np.abs(logz[fin] - ref[fin])))
+    print("d=31 %s max |dlogZ| vs brute force = %.3g" % (prec, err))
+    assert err < {"fp64": 1e-10, "fp32plain": 1e-3, "bf16": 1e-2}[prec]
+
+
+def test_empty_and_ragged_segments(dev):
+    """A segment with no syndromes next to ragged ones (1 and 7 syndromes)
+    in one call: nothing is written for the empty one and the others equal
+    their single-segment results."""
+    segs, alone = [], []
+    for d, count in ((5, 0), (7, 1), (9, 7)):
+        r = synth.depolarizing(d, 0.1)
+        smp = synth.sample(d, r, max(count, 1), seed=d)
+        syn = smp["syndromes"][:count]
+        segs.append(tn.SegmentInput(d, 8, torch.from_numpy(np.ascontiguousarray(syn)).to(dev),
+                                    torch.from_numpy(r).to(dev), None, "fp32"))
+    outs = tn.decode_segments(segs)
+    assert outs[0].logz.shape == (0, 4)
+    for s, o in zip(segs[1:], outs[1:]):
+        a = tn.decode_segments([s])[0]
+        assert torch.equal(a.logz, o.logz) and torch.equal(a.cls, o.cls)

@@ -292,7 +292,8 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
         // M = (Qf^T W) S U'^T; keep the Dn largest singular values
         for_2d(k2, k2, [&](int r, int c) { Vv[r * ldl + c] = r == c ? Fac(1) : Fac(0); });
         __syncthreads();
-        jacobi_svd<Fac>(Lt, kr, k2, ldl, Vv, ldl, SplitTol<Fac>::v, w.s_flag, dred, w.nrm, perm);
+        // the data carry the rounding of the storage type Real, whatever Fac is
+        jacobi_svd<Fac>(Lt, kr, k2, ldl, Vv, ldl, SplitTol<Fac>::v, (double)Eps<Real>::v, w.s_flag, dred, w.nrm, perm);
         for (int c = tid; c < k2; c += NT) {
           double s2 = 0;
           for (int r = 0; r < kr; ++r) s2 += (double)Lt[c * ldl + r] * (double)Lt[c * ldl + r];

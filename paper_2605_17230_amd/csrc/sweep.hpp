@@ -527,9 +527,10 @@ __device__ inline void lq_form_q_any(Real* X, int m, int n, int ld, const Real* 
 // these tests, columns at the rounding floor keep rotating forever.  The
 // iteration stops after a sweep in which no rotated pair had a cosine above
 // sqrt(tol / cols): with quadratic convergence the pairs are then below tol.
-// lst: int scratch of cols entries.  Returns the number of sweeps.
+// eps: rounding unit of the data (of the storage type, which may be coarser
+// than Real).  lst: int scratch of cols entries.  Returns the number of sweeps.
 template <typename Real>
-__device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv, double tol, int* flag,
+__device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv, double tol, double eps, int* flag,
                           double* red, double* nrm, int* lst) {
   constexpr int MAXR = 4;  // rows (and V rows) lane + j G, j < MAXR, live in registers; the rest stream from LDS
   if (cols < 2) return 0;
@@ -545,7 +546,7 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
   __syncthreads();
   double nf2 = 0;
   for (int c = 0; c < cols; ++c) nf2 += nrm[c];  // same order in every thread
-  const double keps = sqrt((double)rows) * (double)Eps<Real>::v;
+  const double keps = sqrt((double)rows) * eps;
   const double floor2 = keps * keps * nf2;
   int nlive = 0;
   for (int c = 0; c < cols; ++c) nlive += nrm[c] > floor2;

@@ -16,25 +16,6 @@
 
 namespace tnmld {
 
-// Copy an MPS between the site regions and a compact buffer (sites back to
-// back, Dl*q*Dr elements each).  dims(J) -> (Dl, q, Dr).  Collective.
-template <typename Real, typename Dims>
-__device__ inline void mps_pack(const Real* scr, const int64_t* region, int nsite, Dims dims, Real* out, bool to_regions,
-                                Real* regions_out) {
-  int64_t off = 0;
-  for (int J = 0; J < nsite; ++J) {
-    int Dl, q, Dr;
-    dims(J, Dl, q, Dr);
-    const int sz = Dl * q * Dr;
-    if (to_regions)
-      for (int e = threadIdx.x; e < sz; e += NT) regions_out[region[J] + e] = out[off + e];
-    else
-      for (int e = threadIdx.x; e < sz; e += NT) out[off + e] = scr[region[J] + e];
-    off += sz;
-  }
-  __syncthreads();
-}
-
 // Environments of row u and the derivative of log Z with respect to the
 // weights of every qubit on it.  top: compact Psi_{u-1} (dims of the forward
 // row's input), bot: Phi_u in site regions (dims of the bottom-up row's

@@ -364,6 +364,82 @@ __device__ inline double mps_close(const Real* scr, const int64_t* region, const
   return tot > 0.0 ? log(tot) : -INFINITY;
 }
 
+// Copy an MPS between the site regions and a compact buffer (sites back to
+// back, Dl*q*Dr elements each).  dims(J) -> (Dl, q, Dr).  Collective.
+template <typename Real, typename Dims>
+__device__ inline void mps_pack(const Real* scr, const int64_t* region, int nsite, Dims dims, Real* out, bool to_regions,
+                                Real* regions_out) {
+  int64_t off = 0;
+  for (int J = 0; J < nsite; ++J) {
+    int Dl, q, Dr;
+    dims(J, Dl, q, Dr);
+    const int sz = Dl * q * Dr;
+    if (to_regions)
+      for (int e = threadIdx.x; e < sz; e += NT) regions_out[region[J] + e] = out[off + e];
+    else
+      for (int e = threadIdx.x; e < sz; e += NT) out[off + e] = scr[region[J] + e];
+    off += sz;
+  }
+  __syncthreads();
+}
+
+// Forward contraction of the four cosets of syndrome b.  The rows before
+// H->shared_rows touch no qubit of the logical representatives, so they are
+// contracted once; the MPS after them is saved to snap (mps_elems) and each
+// coset continues from it.  Writes logz[b][label] for the four cosets; a
+// prefix that vanishes makes all four -inf.  Collective.
+template <typename Real, typename Fac, int GM = GEMM_VALU>
+__device__ void contract_syndrome(const JobDev& job, int64_t b, uint8_t* smem, const LdsLayout& lay, Real* scr,
+                                  Real* snap) {
+  const uint8_t* plan = job.plan;
+  const PlanHeader* H = reinterpret_cast<const PlanHeader*>(plan);
+  const int n = H->n, m = H->m, nsite = H->nsite, nstep = H->nstep;
+  const int ushare = H->shared_rows < nstep ? H->shared_rows : nstep;
+  const SiteStep* steps = reinterpret_cast<const SiteStep*>(plan + H->steps_ofs);
+  const uint8_t* codes = plan + H->codes_ofs;
+  const CheckDesc* checks = reinterpret_cast<const CheckDesc*>(plan + H->checks_ofs);
+  const int64_t* region = reinterpret_cast<const int64_t*>(plan + H->region_ofs);
+  const int16_t* fin = reinterpret_cast<const int16_t*>(plan + H->final_ofs);
+  __shared__ int s_flags[2];
+  __shared__ int s_label;
+  Work<Real, Fac> w = carve<Real, Fac>(smem, lay, s_flags);
+  const int model = job.model_index ? job.model_index[b] : 0;
+  const double* rates = job.rates + (int64_t)model * n * 3;
+  const SiteStep* rowS = steps + (int64_t)ushare * nsite;
+  auto dims = [rowS](int J, int& Dl, int& q, int& Dr) {
+    Dl = rowS[J].Dl_old;
+    q = rowS[J].qi;
+    Dr = rowS[J].Dr_old;
+  };
+  // common prefix (coset 0's reference error; the others differ only later)
+  prep_reference(H, checks, job.syn + b * m, 0, w.syn, w.fbits, &s_label);
+  mps_ones(scr, region, plan + H->init_qi_ofs, nsite);
+  double base = 0.0;
+  bool alive = true;
+  for (int u = 0; u < ushare && alive; ++u)
+    alive = row_step<Real, Fac, GM>(steps + (int64_t)u * nsite, nsite, codes, rates, scr, region, w, base);
+  if (!alive) {
+    for (int mlog = 0; mlog < 4; ++mlog) {
+      const int label = prep_reference(H, checks, job.syn + b * m, mlog, w.syn, w.fbits, &s_label);
+      if (threadIdx.x == 0) job.logz[b * 4 + label] = -INFINITY;
+      __syncthreads();
+    }
+    return;
+  }
+  if (ushare < nstep) mps_pack(scr, region, nsite, dims, snap, false, scr);
+  for (int mlog = 0; mlog < 4; ++mlog) {
+    if (mlog > 0) mps_pack(scr, region, nsite, dims, snap, true, scr);
+    const int label = prep_reference(H, checks, job.syn + b * m, mlog, w.syn, w.fbits, &s_label);
+    double logscale = base;
+    bool ok = true;
+    for (int u = ushare; u < nstep && ok; ++u)
+      ok = row_step<Real, Fac, GM>(steps + (int64_t)u * nsite, nsite, codes, rates, scr, region, w, logscale);
+    const double lz = ok ? logscale + mps_close<Real, Fac>(scr, region, fin, nsite, w.sig) : -INFINITY;
+    if (threadIdx.x == 0) job.logz[b * 4 + label] = lz;
+    __syncthreads();
+  }
+}
+
 // Forward contraction of one (syndrome b, coset mlog): log Z (FP64); *label
 // receives the class the coset belongs to.  Collective.
 template <typename Real, typename Fac, int GM = GEMM_VALU>

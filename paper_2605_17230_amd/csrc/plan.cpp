@@ -79,8 +79,12 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
   h.nstep = nstep;
   h.chi = chi;
   h.group = group;
-  h.lx_col = 0;
-  h.lz_row = 0;
+  // logical representatives on the last column / row: the anti-diagonal rows
+  // u = r + c they touch start at u = d - 1, so the first d - 1 rows of the
+  // sweep are common to the four cosets of a syndrome
+  h.lx_col = d - 1;
+  h.lz_row = d - 1;
+  h.shared_rows = std::min(h.lx_col, h.lz_row);
 
   // variables before step 0: column w holds corner sum -2 (w even) or -1 (w odd)
   for (int J = 0; J < nsite; ++J) {

@@ -65,7 +65,7 @@ struct CheckDesc {
 
 struct PlanHeader {  // device-visible, followed by the tables at the offsets below
   int32_t d, n, m, nsite, nstep, chi, group;
-  int32_t lx_col, lz_row;  // logical representatives: X on column lx_col, Z on row lz_row
+  int32_t lx_col, lz_row;  // logical representatives: X on column lx_col, Z on row lz_row (both d-1)
   int32_t steps_ofs;    // SiteStep[nstep][nsite]
   int32_t codes_ofs;    // uint8 codes
   int32_t checks_ofs;   // CheckDesc[m]
@@ -89,7 +89,8 @@ struct PlanHeader {  // device-visible, followed by the tables at the offsets be
   int32_t max_V;    // (kr + 1) * kr                  right rotations
   int32_t max_Q;    // k * qo * kr                    staged orthonormal site
   int32_t max_kr, max_n, max_m, max_rows, max_bond;
-  int32_t pad;
+  int32_t shared_rows;  // rows 0..shared_rows-1 touch no qubit of the logical representatives:
+                        // their MPOs, hence the MPS after them, are the same for all four cosets
   double flops_fwd; // counted flops of one contraction (see count in plan.cpp)
 };
 

@@ -39,11 +39,15 @@
 
 namespace tnmld {
 
+// Forward: persistent work-groups take syndromes (all four cosets each) from
+// an atomic counter.  Per-group scratch: the MPS site regions, then (at
+// snap_ofs elements) the saved MPS after the rows common to the cosets.
 template <typename Real, typename Fac, int GM>
 __global__ __launch_bounds__(NT) void fwd_kernel(JobTable jt, unsigned long long* counter, char* scratch,
-                                                  int64_t scratch_stride, LdsLayout lay) {
+                                                  int64_t scratch_stride, int64_t snap_ofs, LdsLayout lay) {
   extern __shared__ __align__(16) uint8_t smem[];
   Real* scr = reinterpret_cast<Real*>(scratch + (int64_t)blockIdx.x * scratch_stride);
+  Real* snap = scr + snap_ofs;
   __shared__ long long s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter, 1ull);
@@ -54,12 +58,7 @@ __global__ __launch_bounds__(NT) void fwd_kernel(JobTable jt, unsigned long long
     int jb = 0;
     while (jb + 1 < jt.n && jt.j[jb + 1].item_begin <= item) ++jb;
     const JobDev& job = jt.j[jb];
-    const int64_t local = item - job.item_begin;
-    const int64_t b = local >> 2;
-    const int mlog = (int)(local & 3);
-    int label = 0;
-    const double lz = contract_one<Real, Fac, GM>(job, b, mlog, smem, lay, scr, &label);
-    if (threadIdx.x == 0) job.logz[b * 4 + label] = lz;
+    contract_syndrome<Real, Fac, GM>(job, item - job.item_begin, smem, lay, scr, snap);
     __syncthreads();
   }
 }
@@ -316,9 +315,10 @@ int validate(const tn_segment* segs, int32_t nseg) {
 
 struct Launch {
   int precision;
-  JobTable jt;
+  JobTable jt;  // forward items are syndromes
   PlanHeader merged;
-  int64_t scratch_elems;
+  int64_t scratch_elems;  // site regions (max over the merged plans)
+  int64_t mps_elems;      // one compact MPS (max over the merged plans)
   int nwg;  // persistent work-groups of this launch
 };
 
@@ -357,9 +357,10 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
       j.count = s.count;
       j.item_begin = items;
       j.n_models = s.n_models;
-      items += 4 * s.count;
+      items += s.count;
       merge_maxima(&L.merged, dp->plan.h);
       L.scratch_elems = std::max<int64_t>(L.scratch_elems, dp->plan.h.scratch_elems);
+      L.mps_elems = std::max<int64_t>(L.mps_elems, dp->plan.h.mps_elems);
       int tw = 0;
       {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -380,7 +381,7 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
     if (w < 1) return fail(TN_EUNSUPPORTED, "LDS of the merged plans exceeds one CU");
     L.nwg = w * di.cus;
     *nwg = std::max(*nwg, L.nwg);
-    bytes += (size_t)L.nwg * align_up((size_t)L.scratch_elems * real_bytes(L.precision));
+    bytes += (size_t)L.nwg * align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
   }
   *ws_bytes = bytes;
   return TN_OK;
@@ -392,8 +393,9 @@ int launch_fwd(const Launch& L, int nwg, char* ws_scratch, unsigned long long* c
   auto kern = fwd_kernel<Real, Fac, GM>;
   if (int rc = ensure_lds_attr(reinterpret_cast<const void*>(kern), lay.bytes)) return rc;
   zero_counter<<<1, 64, 0, st>>>(counter);
-  const int64_t stride = (int64_t)align_up((size_t)L.scratch_elems * sizeof(Real));
-  hipLaunchKernelGGL(kern, dim3(nwg), dim3(NT), lay.bytes, st, L.jt, counter, ws_scratch, stride, lay);
+  const int64_t stride = (int64_t)align_up((size_t)(L.scratch_elems + L.mps_elems) * sizeof(Real));
+  const int64_t snap_ofs = L.scratch_elems;
+  hipLaunchKernelGGL(kern, dim3(nwg), dim3(NT), lay.bytes, st, L.jt, counter, ws_scratch, stride, snap_ofs, lay);
   if (hipGetLastError() != hipSuccess) return fail(TN_EDEVICE, "kernel launch failed");
   return TN_OK;
 }
@@ -416,7 +418,7 @@ int run_forward(const tn_segment* segs, int32_t nseg, void* workspace, size_t ws
   for (auto& L : launches) {
     unsigned long long* counter = reinterpret_cast<unsigned long long*>(base) + li;
     char* scr = base + off;
-    off += (size_t)L.nwg * align_up((size_t)L.scratch_elems * real_bytes(L.precision));
+    off += (size_t)L.nwg * align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
     if (L.precision == TN_FP64) rc = launch_fwd<double, double, GEMM_VALU>(L, L.nwg, scr, counter, st);
     else if (L.precision == TN_FP32) rc = launch_fwd<float, double, GEMM_VALU>(L, L.nwg, scr, counter, st);
     else if (L.precision == TN_BF16) rc = launch_fwd<float, float, BF16_GEMM_MODE>(L, L.nwg, scr, counter, st);
@@ -457,6 +459,15 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
   bl->precision = L.precision;
   bl->jt = L.jt;
   bl->merged = L.merged;
+  {
+    // backward items are (syndrome, coset) pairs
+    int64_t items = 0;
+    for (int i = 0; i < bl->jt.n; ++i) {
+      bl->jt.j[i].item_begin = items;
+      items += 4 * bl->jt.j[i].count;
+    }
+    bl->jt.nitems = items;
+  }
   // map jobs back to segments (same order as plan_launches: by decreasing d, stable)
   std::vector<int> order(nseg);
   for (int i = 0; i < nseg; ++i) order[i] = i;

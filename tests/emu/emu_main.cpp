@@ -1,5 +1,6 @@
-// Host entry points that run the device code of the sweep (forward and
-// adjoint) one (syndrome, coset) item at a time on NT host threads.  Test
+// Host entry points that run the device code of the sweep on NT host threads:
+// the forward one syndrome (four cosets) at a time, the adjoint one
+// (syndrome, coset) item at a time.  Test
 // infrastructure only: built by tests/test_kernel_emulation.py.
 #include "emu_hip.hpp"
 
@@ -42,16 +43,14 @@ int forward(int d, int chi, int group, const double* rates, const uint8_t* syn, 
   Plan p;
   if (!build_plan(d, chi, group, &p).empty()) return -1;
   const LdsLayout lay = lds_layout(p.h, sizeof(Real), sizeof(Fac));
-  std::vector<double> smem(lay.bytes / 8 + 16), scr(p.h.scratch_elems * sizeof(Real) / 8 + 16);
+  std::vector<double> smem(lay.bytes / 8 + 16), scr(p.h.scratch_elems * sizeof(Real) / 8 + 16),
+      snap(p.h.mps_elems * sizeof(Real) / 8 + 16);
   JobDev job{p.blob.data(), rates, nullptr, syn, logz, nullptr, nullptr, count, 0, 0, 1, 0};
   Barriers bars;
   for (int b = 0; b < count; ++b)
-    for (int m = 0; m < 4; ++m)
-      run_block([&](int t) {
-        int label = 0;
-        const double lz = contract_one<Real, Fac>(job, b, m, (uint8_t*)smem.data(), lay, (Real*)scr.data(), &label);
-        if (t == 0) logz[b * 4 + label] = lz;
-      });
+    run_block([&](int) {
+      contract_syndrome<Real, Fac>(job, b, (uint8_t*)smem.data(), lay, (Real*)scr.data(), (Real*)snap.data());
+    });
   return 0;
 }
 

@@ -118,7 +118,7 @@ def bench_adjoint(a, torch, tn, synth, dev, stream):
     seg = tn.SegmentInput(s["d"], s["chi"], torch.from_numpy(s["syndromes"]).to(dev),
                           torch.from_numpy(s["rates"]).to(dev), None, prec)
     gw = torch.ones(n, dtype=torch.float64, device=dev)
-    fwd_flops = 4.0 * n * tn.plan_info(s["d"], s["chi"], prec)["flops"]
+    info = tn.plan_info(s["d"], s["chi"], prec)
     print("bench: adjoint d=%d chi=%d %s, %d syndromes" % (s["d"], s["chi"], prec, n), file=sys.stderr, flush=True)
     for _ in range(a.warmup):
         tn.coset_loglik_backward([seg], [gw])
@@ -138,10 +138,11 @@ def bench_adjoint(a, torch, tn, synth, dev, stream):
     e1.record(stream)
     torch.cuda.synchronize()
     ms_fwd = e0.elapsed_time(e1)
-    # counted work of the backward: forward sweep with checkpoints, recompute of
-    # every segment, transposed bottom-up sweep (three forward sweeps' worth of
-    # row steps) plus the forward pass that supplies log Z; environments excluded
-    flops = 4.0 * fwd_flops
+    # counted work: the forward pass that supplies log Z (shared rows once per
+    # syndrome), then per coset the checkpointed top sweep, the recompute of
+    # every segment and the transposed bottom-up sweep (three sweeps' worth of
+    # row steps); the row environments are not counted
+    flops = n * (info["flops_syndrome"] + 12.0 * info["flops"])
     achieved = flops / (ms_step / 1e3) / 1e12
     g = grads[0].cpu().numpy()
     out = {
@@ -201,7 +202,8 @@ def main():
             out.append(tn.SegmentInput(s["d"], s["chi"], sy, rt, mi, prec))
         return out
 
-    flops_per_step = sum(4.0 * len(s["syndromes"]) * tn.plan_info(s["d"], s["chi"], a.precision)["flops"]
+    # counted work as executed: per syndrome, the rows common to its four cosets once, the rest four times
+    flops_per_step = sum(len(s["syndromes"]) * tn.plan_info(s["d"], s["chi"], a.precision)["flops_syndrome"]
                          for s in segs_h)
     segs = inputs(a.precision)
     print("bench: %s, %s, %d warmup + %d timed steps" % (workload, a.precision, a.warmup, a.steps),

@@ -134,8 +134,10 @@ int tn_code_stabilizers(int32_t d, int32_t* type_out, int32_t* support_out);
 /* HOST helper: properties of the contraction plan for (d, chi, precision):
  * info[0] counted forward flops per (syndrome, coset), info[1] scratch bytes
  * per work-group, info[2] LDS bytes per work-group, info[3] sites per row,
- * info[4] rows, info[5] columns per site, info[6] work-groups per CU.
- * info: host array of >= 7 doubles.  Returns TN_OK or a tn_status. */
+ * info[4] rows, info[5] columns per site, info[6] work-groups per CU,
+ * info[7] counted forward flops per syndrome as executed (the rows common to
+ * the four cosets once, the rest four times).
+ * info: host array of >= 8 doubles.  Returns TN_OK or a tn_status. */
 int tn_plan_info(int32_t d, int32_t chi, int32_t precision, double* info);
 
 /* HOST helper: launch shape for (d, chi, precision) used by later calls in

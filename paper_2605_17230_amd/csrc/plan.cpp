@@ -244,6 +244,7 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
       if (S.Dr_new < k2)                                                // bond truncated:
         flops += svd_flops(S.kr, k2) + 2.0 * R * k2 * S.Dr_new;        //   SVD of R factor + A = Q W
     }
+    if (u + 1 == h.shared_rows) h.flops_shared = flops;
   }
   h.flops_fwd = flops;
 

@@ -91,7 +91,8 @@ struct PlanHeader {  // device-visible, followed by the tables at the offsets be
   int32_t max_kr, max_n, max_m, max_rows, max_bond;
   int32_t shared_rows;  // rows 0..shared_rows-1 touch no qubit of the logical representatives:
                         // their MPOs, hence the MPS after them, are the same for all four cosets
-  double flops_fwd; // counted flops of one contraction (see count in plan.cpp)
+  double flops_fwd;     // counted flops of one coset's contraction (see count in plan.cpp)
+  double flops_shared;  // the part of flops_fwd spent in rows 0..shared_rows-1
 };
 
 struct Plan {

@@ -648,6 +648,7 @@ int tn_plan_info(int32_t d, int32_t chi, int32_t precision, double* info) {
   info[4] = p.h.nstep;
   info[5] = g;
   info[6] = wgs_for((int)info[2], fwd_kernel_of(precision));
+  info[7] = p.h.flops_shared + 4.0 * (p.h.flops_fwd - p.h.flops_shared);
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_tune.find(std::make_tuple(d, chi, precision));

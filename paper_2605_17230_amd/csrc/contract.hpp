@@ -440,31 +440,5 @@ __device__ void contract_syndrome(const JobDev& job, int64_t b, uint8_t* smem, c
   }
 }
 
-// Forward contraction of one (syndrome b, coset mlog): log Z (FP64); *label
-// receives the class the coset belongs to.  Collective.
-template <typename Real, typename Fac, int GM = GEMM_VALU>
-__device__ double contract_one(const JobDev& job, int64_t b, int mlog, uint8_t* smem, const LdsLayout& lay,
-                               Real* scr, int* label) {
-  const uint8_t* plan = job.plan;
-  const PlanHeader* H = reinterpret_cast<const PlanHeader*>(plan);
-  const int n = H->n, m = H->m, nsite = H->nsite, nstep = H->nstep;
-  const SiteStep* steps = reinterpret_cast<const SiteStep*>(plan + H->steps_ofs);
-  const uint8_t* codes = plan + H->codes_ofs;
-  const CheckDesc* checks = reinterpret_cast<const CheckDesc*>(plan + H->checks_ofs);
-  const int64_t* region = reinterpret_cast<const int64_t*>(plan + H->region_ofs);
-  __shared__ int s_flags[2];
-  __shared__ int s_label;
-  Work<Real, Fac> w = carve<Real, Fac>(smem, lay, s_flags);
-  const int model = job.model_index ? job.model_index[b] : 0;
-  const double* rates = job.rates + (int64_t)model * n * 3;
-  *label = prep_reference(H, checks, job.syn + b * m, mlog, w.syn, w.fbits, &s_label);
-  mps_ones(scr, region, plan + H->init_qi_ofs, nsite);
-  double logscale = 0.0;
-  for (int u = 0; u < nstep; ++u)
-    if (!row_step<Real, Fac, GM>(steps + (int64_t)u * nsite, nsite, codes, rates, scr, region, w, logscale))
-      return -INFINITY;
-  const int16_t* fin = reinterpret_cast<const int16_t*>(plan + H->final_ofs);
-  return logscale + mps_close<Real, Fac>(scr, region, fin, nsite, w.sig);
-}
 
 }  // namespace tnmld

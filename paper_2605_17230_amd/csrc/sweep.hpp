@@ -15,7 +15,11 @@
 
 namespace tnmld {
 
-constexpr int NT = 512;
+// Threads per work-group (512; a second build of the forward kernel uses 256).
+#ifndef TNMLD_NT
+#define TNMLD_NT 512
+#endif
+constexpr int NT = TNMLD_NT;
 constexpr int WAVE = 64;
 
 template <typename Real>

@@ -37,6 +37,13 @@
 #define BF16_GEMM_MODE GEMM_BF16X3
 #endif
 
+// The forward kernel built for 256-thread work-groups (tnmld_small.hip).
+namespace tnmld_small {
+int small_wgs_per_cu(int precision, int lds_bytes);
+int launch_fwd_small(int precision, const void* jt, unsigned long long* counter, char* scratch, int64_t stride,
+                     int64_t snap_ofs, const void* lay, int lds_bytes, int nwg, hipStream_t st);
+}  // namespace tnmld_small
+
 namespace tnmld {
 
 // Forward: persistent work-groups take syndromes (all four cosets each) from
@@ -313,7 +320,21 @@ int validate(const tn_segment* segs, int32_t nseg) {
   return TN_OK;
 }
 
+// Plans whose site matrices have at most 32 rows (chi <= 16 with a bond-2
+// MPO) and at most 256 columns run on the 256-thread build of the forward
+// kernel when at least two of its work-groups fit a CU (LDS and registers).
+constexpr int kSmallNT = 256;
+bool small_plan(const PlanHeader& h, int precision) {
+  if (h.max_m > 2 * (kSmallNT / 16) || h.max_n > 256 || h.max_bond > kSmallNT) return false;
+  const int lb = lds_layout(h, real_bytes(precision), fac_bytes(precision)).bytes;
+  if (lb > kLdsPerCU / 2 - 256) return false;
+  return tnmld_small::small_wgs_per_cu(precision, lb) >= 2;
+}
+
+constexpr int kMaxLaunches = 2 * (TN_FP32_PLAIN + 1);  // one per precision and size class
+
 struct Launch {
+  bool small;  // 256-thread build
   int precision;
   JobTable jt;  // forward items are syndromes
   PlanHeader merged;
@@ -327,7 +348,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Build the launch groups (one per precision) and the workspace layout.
 int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vector<Launch>* out, size_t* ws_bytes,
-                  int* nwg) {
+                  int* nwg, bool allow_small = true) {
   int rc = validate(segs, nseg);
   if (rc) return rc;
   DevInfo di;
@@ -338,8 +359,12 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
   for (int i = 0; i < nseg; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return segs[a].d > segs[b].d; });
   out->clear();
-  for (int prec = TN_FP64; prec <= TN_FP32_PLAIN; ++prec) {
+  for (int launch = 0; launch < kMaxLaunches; ++launch) {
+    const int prec = launch >> 1;
+    const bool small = (launch & 1) != 0;
+    if (small && !allow_small) continue;
     Launch L{};
+    L.small = small;
     L.precision = prec;
     int64_t items = 0;
     for (int oi : order) {
@@ -348,6 +373,7 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
       if (!precision_built(prec)) return fail(TN_EUNSUPPORTED, "precision not built");
       DevPlan* dp = nullptr;
       if ((rc = get_plan(s.d, s.chi, prec, lds_limit, &dp))) return rc;
+      if ((allow_small && small_plan(dp->plan.h, prec)) != small) continue;
       JobDev& j = L.jt.j[L.jt.n++];
       j.plan = dp->dev;
       j.rates = s.rates;
@@ -372,11 +398,15 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
     L.jt.nitems = items;
     if (L.jt.n > 0) out->push_back(L);
   }
-  size_t bytes = align_up(sizeof(unsigned long long) * 4);
+  size_t bytes = align_up(sizeof(unsigned long long) * kMaxLaunches);
   for (auto& L : *out) {
     if (L.merged.max_bond > NT) return fail(TN_EUNSUPPORTED, "bond dimension above the work-group size");
     const int lb = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision)).bytes;
     int w = wgs_for(lb, fwd_kernel_of(L.precision));
+    if (L.small) {
+      const int ws = tnmld_small::small_wgs_per_cu(L.precision, lb);
+      w = std::min(kLdsPerCU / (lb + 256), ws > 0 ? ws : 1);
+    }
     if (L.nwg > 0) w = std::min(w, L.nwg);
     if (w < 1) return fail(TN_EUNSUPPORTED, "LDS of the merged plans exceeds one CU");
     L.nwg = w * di.cus;
@@ -413,12 +443,21 @@ int run_forward(const tn_segment* segs, int32_t nseg, void* workspace, size_t ws
   if (!workspace || ws_bytes < need) return fail(TN_EINVAL, "workspace too small: need " + std::to_string(need));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* base = reinterpret_cast<char*>(workspace);
-  size_t off = align_up(sizeof(unsigned long long) * 4);
+  size_t off = align_up(sizeof(unsigned long long) * kMaxLaunches);
   int li = 0;
   for (auto& L : launches) {
     unsigned long long* counter = reinterpret_cast<unsigned long long*>(base) + li;
     char* scr = base + off;
     off += (size_t)L.nwg * align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
+    if (L.small) {
+      const LdsLayout lay = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision));
+      const int64_t stride = (int64_t)align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
+      if (tnmld_small::launch_fwd_small(L.precision, &L.jt, counter, scr, stride, L.scratch_elems, &lay, lay.bytes,
+                                        L.nwg, st) != 0)
+        return fail(TN_EDEVICE, "kernel launch failed");
+      ++li;
+      continue;
+    }
     if (L.precision == TN_FP64) rc = launch_fwd<double, double, GEMM_VALU>(L, L.nwg, scr, counter, st);
     else if (L.precision == TN_FP32) rc = launch_fwd<float, double, GEMM_VALU>(L, L.nwg, scr, counter, st);
     else if (L.precision == TN_BF16) rc = launch_fwd<float, float, BF16_GEMM_MODE>(L, L.nwg, scr, counter, st);
@@ -448,9 +487,14 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
   int rc = validate(segs, nseg);
   if (rc) return rc;
   if ((rc = device_info(&di))) return rc;
-  if ((rc = plan_launches(segs, nseg, std::min(di.lds_max, kLdsLimit), &launches, &fwd, &nwgf))) return rc;
+  {
+    // the forward pass that supplies log Z runs with its own launch split
+    std::vector<Launch> fl;
+    if ((rc = plan_launches(segs, nseg, std::min(di.lds_max, kLdsLimit), &fl, &fwd, &nwgf, true))) return rc;
+    bl->fwd_bytes = align_up(fwd);
+  }
+  if ((rc = plan_launches(segs, nseg, std::min(di.lds_max, kLdsLimit), &launches, &fwd, &nwgf, false))) return rc;
   if (launches.size() > 1) return fail(TN_EUNSUPPORTED, "backward segments must share one precision");
-  bl->fwd_bytes = align_up(fwd);
   if (launches.empty()) {
     bl->total = bl->fwd_bytes;
     return TN_OK;

@@ -311,12 +311,23 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
         }
         __syncthreads();
         // A[(l,so)][r] = sum_c Qf[c][(l,so)] W[c][perm r];  C[r][c'] = (Lf W)[c'][perm r]
-        for_2d(R, Dn, [&](int lso, int r) {
-          const Fac* w = Vv + perm[r] * ldl;
-          Fac acc = 0;
-          for (int c = 0; c < k2; ++c) acc += Mm[c * ldm + lso] * w[c];
-          g[lso * Dn + r] = Real(acc);
-        });
+#ifndef TNMLD_EMU
+        if constexpr (GM != GEMM_VALU) {
+          // a GEMM (R x k2) . (k2 x Dn): on the bf16 matrix cores like the other contractions of this form
+          gemm_mfma_bf16<GM == GEMM_BF16X3>(
+              R, Dn, k2, [&](int lso, int c) { return (float)Mm[c * ldm + lso]; },
+              [&](int c, int r) { return (float)Vv[perm[r] * ldl + c]; },
+              [&](int lso, int r, float v) { g[lso * Dn + r] = Real(v); });
+        } else
+#endif
+        {
+          for_2d(R, Dn, [&](int lso, int r) {
+            const Fac* w = Vv + perm[r] * ldl;
+            Fac acc = 0;
+            for (int c = 0; c < k2; ++c) acc += Mm[c * ldm + lso] * w[c];
+            g[lso * Dn + r] = Real(acc);
+          });
+        }
         for_2d(Dn, kr, [&](int r, int c) { C[r * kr + c] = Real(Lt[perm[r] * ldl + c]); });
         __syncthreads();
       }

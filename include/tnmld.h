@@ -56,10 +56,12 @@ typedef enum {
   TN_FP64 = 0,       /* every step in FP64 */
   TN_FP32 = 1,       /* MPS and MPO.MPS contractions in FP32; the LQ and SVD
                         factorisations of the truncation in FP64 */
-  TN_BF16 = 2,       /* MPS stored in FP32; the two contraction GEMMs of each
-                        site step (MPO.MPS times the carried factor, carry times
-                        Q) on bf16 MFMA with FP32 accumulation, operands split
-                        into bf16 high and low parts; factorisations in FP32 */
+  TN_BF16 = 2,       /* MPS stored in FP32; the contraction GEMMs of each site
+                        step (MPO.MPS times the carried factor, carry times Q,
+                        and on truncated bonds Q times the kept singular
+                        vectors) on bf16 MFMA with FP32 accumulation, operands
+                        split into bf16 high and low parts; factorisations in
+                        FP32 */
   TN_FP32_PLAIN = 3  /* every contraction and factorisation in FP32 (norms and
                         Jacobi inner products accumulate in FP64); the plain
                         single-precision form */

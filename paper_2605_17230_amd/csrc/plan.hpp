@@ -141,7 +141,9 @@ inline LdsLayout lds_layout(const PlanHeader& h, int rb, int fb) {
   const int32_t lr_end = p;
   p = rl_end > lr_end ? rl_end : lr_end;
   const int32_t nh = h.max_m > h.max_kr ? h.max_m : h.max_kr;
-  const int32_t nv = h.max_n > h.max_rows ? h.max_n : h.max_rows;
+  int32_t nv = h.max_n > h.max_rows ? h.max_n : h.max_rows;
+  // the register LQ stages each reflector over a whole row of lanes (128 or 256 columns)
+  if (nv < (nv <= 128 ? 128 : 256)) nv = nv <= 128 ? 128 : 256;
   o.tau = p; p += pad64b((int64_t)nh * fb);
   o.diag = p; p += pad64b((int64_t)nh * fb);
   o.v = p; p += pad64b((int64_t)2 * nv * fb);

@@ -339,10 +339,11 @@ __device__ void lq_form_q(Real* X, int m, int n, int ld, const Real* tau, Real* 
 // type (FP32 in the FP32 forms: the reflector's leading entry is 1, so the
 // dot keeps the scale of the row's own entry and only terms far below it can
 // underflow); row norms stay FP64.  Only the
-// reflector of each step goes through LDS (staged with explicit zeros and the
-// implicit one in vb + (i & 1) * n, so the row update is branch-free).  The
+// reflector of each step goes through LDS, staged over all 16 NPL columns with
+// explicit zeros (left of i and past n) and the implicit one, in
+// vb + (i & 1) * 16 NPL, so the row update loads it with no bounds test.  The
 // owner of row i + 1 builds the next reflector as soon as it has updated that
-// row: one barrier per step.  vb: LDS scratch of 2n.
+// row: one barrier per step.  vb: LDS scratch of 32 NPL.
 constexpr int LQR_RPG = 2, LQR_NPL = 16;
 __device__ inline bool lq_regs_fit(int m, int n) { return m <= LQR_RPG * (NT / 16) && n <= LQR_NPL * 16; }
 
@@ -382,12 +383,12 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
       t = (beta - x0) / beta;
       scale = 1.0 / (x0 - beta);
     }
-    Real* v = vb + (i & 1) * n;
+    Real* v = vb + (i & 1) * (16 * NPL);
 #pragma unroll
     for (int c = 0; c < NPL; ++c) {
       const int col = lane + 16 * c;
       if (live && col > i) xr[c] = Real((double)xr[c] * scale);
-      if (col < n) v[col] = col < i ? Real(0) : (col == i ? Real(1) : xr[c]);
+      v[col] = col < i ? Real(0) : (col == i ? Real(1) : xr[c]);  // past column n, xr stays 0
     }
     if (lane == 0) {
       tau[i] = Real(t);
@@ -399,13 +400,10 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
   __syncthreads();
   for (int i = 0; i < k; ++i) {
     const double t = red[i & 1];
-    const Real* v = vb + (i & 1) * n;
+    const Real* v = vb + (i & 1) * (16 * NPL);
     Real vv[NPL];
 #pragma unroll
-    for (int c = 0; c < NPL; ++c) {
-      const int col = lane + 16 * c;
-      vv[c] = col < n ? v[col] : Real(0);
-    }
+    for (int c = 0; c < NPL; ++c) vv[c] = v[lane + 16 * c];  // staged with its zeros: no bounds test
 #pragma unroll
     for (int j = 0; j < LQR_RPG; ++j) {
       const int r = grp + NG * j;
@@ -440,12 +438,20 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
 // of Q = [I_k 0] H_{k-1} ... H_0 is e_r - tau_r v_r pushed through
 // H_{r-1}, ..., H_0, which involves no other row of Q, so each lane group
 // builds its rows (r and 2*32-1-r, balancing the step counts) with no barrier,
-// reading the reflectors from X.  One barrier before the rows are stored.
-template <typename Real, int NPL = LQR_NPL>
+// reading the reflectors from X.  The strictly lower part of X (L, already
+// copied out by the caller) is first overwritten with the zeros and the
+// diagonal with the ones of the reflectors, so the loop reads rows with no
+// index tests; FULL (n == 16 NPL) drops the bounds test on the columns too.
+// One barrier before the rows are stored.
+template <typename Real, int NPL, bool FULL>
 __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
   const int k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
   constexpr int NG = NT / 16;
+  for_2d(k, k, [&](int r, int c) {
+    if (c <= r) X[r * ld + c] = c == r ? Real(1) : Real(0);
+  });
+  __syncthreads();
   Real q[LQR_RPG][NPL];
 #pragma unroll
   for (int j = 0; j < LQR_RPG; ++j) {
@@ -457,20 +463,19 @@ __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
 #pragma unroll
       for (int c = 0; c < NPL; ++c) {
         const int col = lane + 16 * c;
-        const Real vc = col < r ? Real(0) : (col == r ? Real(1) : (col < n ? xr[col] : Real(0)));
+        const Real vc = (FULL || col < n) ? xr[col] : Real(0);
         q[j][c] = (col == r ? Real(1) : Real(0)) - t * vc;
       }
     }
     for (int i = r - 1; i >= 0; --i) {
-      const Real t = tau[i];
-      if (t == Real(0)) continue;
+      const Real t = tau[i];  // tau = 0 (no reflection) leaves q as it is
       const Real* xi = X + i * ld;
       Real vv[NPL];
       Real dp[4] = {Real(0), Real(0), Real(0), Real(0)};
 #pragma unroll
       for (int c = 0; c < NPL; ++c) {
         const int col = lane + 16 * c;
-        vv[c] = col < i ? Real(0) : (col == i ? Real(1) : (col < n ? xi[col] : Real(0)));
+        vv[c] = (FULL || col < n) ? xi[col] : Real(0);
         dp[c & 3] += q[j][c] * vv[c];
       }
       const Real dot = group_sum((dp[0] + dp[1]) + (dp[2] + dp[3]), 16);
@@ -487,7 +492,7 @@ __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
 #pragma unroll
     for (int c = 0; c < NPL; ++c) {
       const int col = lane + 16 * c;
-      if (col < n) X[r * ld + col] = q[j][c];
+      if (FULL || col < n) X[r * ld + col] = q[j][c];
     }
   }
   __syncthreads();
@@ -506,8 +511,10 @@ __device__ inline void lq_factor_any(Real* X, int m, int n, int ld, Real* tau, R
 template <typename Real>
 __device__ inline void lq_form_q_any(Real* X, int m, int n, int ld, const Real* tau, Real* v) {
   if (lq_regs_fit(m, n)) {
-    if (n <= 128) lq_form_q_regs<Real, 8>(X, m, n, ld, tau);
-    else lq_form_q_regs<Real, 16>(X, m, n, ld, tau);
+    if (n == 128) lq_form_q_regs<Real, 8, true>(X, m, n, ld, tau);
+    else if (n == 256) lq_form_q_regs<Real, 16, true>(X, m, n, ld, tau);
+    else if (n < 128) lq_form_q_regs<Real, 8, false>(X, m, n, ld, tau);
+    else lq_form_q_regs<Real, 16, false>(X, m, n, ld, tau);
   } else {
     lq_form_q<Real>(X, m, n, ld, tau, v);
   }

@@ -364,42 +364,46 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
       x[j][c] = (r < m && col < n) ? X[r * ld + col] : Real(0);
     }
   }
-  // reflector of row i held in slot j of this group (all 16 lanes call it)
+  // reflector of row i held in slot j of this group (all 16 lanes call it).
+  // Norm and reflector scalars in FP64; the tail is scaled in the storage type.
   auto reflector = [&](int i, Real* xr) {
-    double tp[4] = {0.0, 0.0, 0.0, 0.0}, x0 = 0.0;  // four partial sums: short FMA chains
+    double tp[4] = {0.0, 0.0, 0.0, 0.0};  // four partial sums: short FMA chains
+    Real x0r = Real(0);
 #pragma unroll
     for (int c = 0; c < NPL; ++c) {
       const int col = lane + 16 * c;
-      if (col > i) tp[c & 3] += (double)xr[c] * (double)xr[c];
-      if (col == i) x0 = (double)xr[c];
+      const Real xt = col > i ? xr[c] : Real(0);
+      tp[c & 3] += (double)xt * (double)xt;
+      if (col == i) x0r = xr[c];
     }
-    double t2 = group_sum((tp[0] + tp[1]) + (tp[2] + tp[3]), 16);
-    x0 = group_sum(x0, 16);  // one lane holds it
+    const double t2 = group_sum((tp[0] + tp[1]) + (tp[2] + tp[3]), 16);
+    const double x0 = (double)group_sum(x0r, 16);  // one lane holds it: the sum is exact
     const double nrm = sqrt(t2 + x0 * x0);
     const bool live = t2 > 0.0 && nrm > TinyNorm<Real>::v;
-    double beta = x0, t = 0.0, scale = 0.0;
+    double beta = x0, td = 0.0, sd = 0.0;
     if (live) {
       beta = x0 >= 0.0 ? -nrm : nrm;
-      t = (beta - x0) / beta;
-      scale = 1.0 / (x0 - beta);
+      td = (beta - x0) / beta;
+      sd = 1.0 / (x0 - beta);
     }
+    const Real t = Real(td), scale = Real(sd);
     Real* v = vb + (i & 1) * (16 * NPL);
 #pragma unroll
     for (int c = 0; c < NPL; ++c) {
       const int col = lane + 16 * c;
-      if (live && col > i) xr[c] = Real((double)xr[c] * scale);
+      if (live && col > i) xr[c] *= scale;
       v[col] = col < i ? Real(0) : (col == i ? Real(1) : xr[c]);  // past column n, xr stays 0
     }
     if (lane == 0) {
-      tau[i] = Real(t);
+      tau[i] = t;
       diag[i] = Real(beta);
-      red[i & 1] = t;
+      red[i & 1] = (double)t;
     }
   };
   if (k > 0 && grp == 0) reflector(0, x[0]);
   __syncthreads();
   for (int i = 0; i < k; ++i) {
-    const double t = red[i & 1];
+    const Real t = Real(red[i & 1]);
     const Real* v = vb + (i & 1) * (16 * NPL);
     Real vv[NPL];
 #pragma unroll
@@ -408,12 +412,11 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
     for (int j = 0; j < LQR_RPG; ++j) {
       const int r = grp + NG * j;
       if (r > i && r < m) {
-        if (t != 0.0) {
+        if (t != Real(0)) {
           Real dp[4] = {Real(0), Real(0), Real(0), Real(0)};
 #pragma unroll
           for (int c = 0; c < NPL; ++c) dp[c & 3] += x[j][c] * vv[c];
-          const double dot = (double)group_sum((dp[0] + dp[1]) + (dp[2] + dp[3]), 16);
-          const Real w = Real(dot * t);
+          const Real w = group_sum((dp[0] + dp[1]) + (dp[2] + dp[3]), 16) * t;
 #pragma unroll
           for (int c = 0; c < NPL; ++c) x[j][c] -= w * vv[c];
         }

@@ -41,7 +41,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16")
     ap.add_argument("--compare", default="fp32plain", help="second form timed once ('' to skip)")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5", "fit"])
+    ap.add_argument("--fit-steps", type=int, default=60, help="Adam steps of the fit workload")
+    ap.add_argument("--fit-batch", type=int, default=1024, help="syndromes per step of the fit workload")
     ap.add_argument("--count", type=int, default=COUNT)
     ap.add_argument("--fp64-sample", type=int, default=512, help="syndromes decoded in FP64 for the error report")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -161,6 +163,44 @@ def bench_adjoint(a, torch, tn, synth, dev, stream):
     print(json.dumps(out), flush=True)
 
 
+def bench_fit(a, torch, tn, synth, dev):
+    """Noise-model fitting on the gradient workload: Adam on the per-qubit log
+    rates from a uniform start, one forward + backward per step on a random
+    mini-batch of the syndromes."""
+    s = synth.config_inputs("C5")[0]
+    prec = a.precision if a.precision != "bf16" else "fp32"
+    d, chi = s["d"], s["chi"]
+    syn = torch.from_numpy(s["syndromes"]).to(dev)
+    true = torch.from_numpy(np.log(s["rates"][0])).to(dev)
+    theta0 = torch.full_like(true, float(np.log(s["rates"][0].mean())))
+    print("bench: fit d=%d chi=%d %s, %d syndromes, %d steps of %d" % (d, chi, prec, len(syn), a.fit_steps,
+                                                                       a.fit_batch), file=sys.stderr, flush=True)
+    tn.fit_log_rates(syn, d, chi, theta0, steps=1, batch=a.fit_batch, precision=prec)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    theta, hist = tn.fit_log_rates(syn, d, chi, theta0, steps=a.fit_steps, lr=0.05, batch=a.fit_batch,
+                                   precision=prec)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    def loss(th):
+        with torch.no_grad():
+            return float(-tn.log_posterior(th, syn, d, chi, prec)[0].mean())
+
+    out = {
+        "metric": "syndromes/s through the noise fit (forward + adjoint + Adam step) at d=11 chi=24",
+        "value": a.fit_steps * a.fit_batch / dt, "unit": "syndromes/s", "n_gpus": 1, "steps": a.fit_steps,
+        "warmup": 1, "ms_per_step": dt / a.fit_steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
+        "config": {"workload": "fit of 363 log rates to %d syndromes of the d=11 gradient model, chi=24, "
+                               "mini-batch %d, Adam lr 0.05" % (len(syn), a.fit_batch), "precision": prec},
+        "loss": {"start": loss(theta0), "end": loss(theta), "true_rates": loss(true)},
+        "mean_abs_log_rate_error": {"start": float((theta0 - true).abs().mean()),
+                                    "end": float((theta - true).abs().mean())},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -179,6 +219,9 @@ def main():
     stream = torch.cuda.current_stream(dev)
     if a.workload == "c5":
         bench_adjoint(a, torch, tn, synth, dev, stream)
+        return
+    if a.workload == "fit":
+        bench_fit(a, torch, tn, synth, dev)
         return
     if a.workload == "c3":
         rates = synth.depolarizing(D, P)

@@ -6,6 +6,7 @@ marshals arguments.  See include/tnmld.h for the C ABI.
 from ._lib import TNError, lib, LIB_PATH  # noqa: F401
 from .api import (SegmentInput, SegmentOutput, code_stabilizers, coset_loglik, coset_loglik_backward,  # noqa: F401
                   decode, decode_segments, log_posterior, plan_info, set_tuning)
+from .fit import fit_log_rates  # noqa: F401
 
 from . import tune as _tune  # noqa: E402
 
@@ -15,4 +16,4 @@ except Exception:  # a missing or unreadable cache keeps the defaults
     pass
 
 __all__ = ["TNError", "SegmentInput", "SegmentOutput", "coset_loglik", "coset_loglik_backward", "log_posterior", "decode", "decode_segments",
-           "plan_info", "set_tuning", "code_stabilizers", "lib", "LIB_PATH"]
+           "fit_log_rates", "plan_info", "set_tuning", "code_stabilizers", "lib", "LIB_PATH"]

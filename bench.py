@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16")
     ap.add_argument("--compare", default="fp32plain", help="second form timed once ('' to skip)")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5", "fit"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5", "fit", "study"])
+    ap.add_argument("--study-count", type=int, default=4096, help="syndromes per (d, p) point of the study")
     ap.add_argument("--fit-steps", type=int, default=60, help="Adam steps of the fit workload")
     ap.add_argument("--fit-batch", type=int, default=1024, help="syndromes per step of the fit workload")
     ap.add_argument("--count", type=int, default=COUNT)
@@ -201,6 +202,52 @@ def bench_fit(a, torch, tn, synth, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_study(a, torch, tn, synth, dev):
+    """Decoder sanity on the same kernels: logical error rate against p and d
+    at chi = 32 (the curves should cross near the depolarizing MLD threshold,
+    about 18.9 %, paper Sec. 3.1.2), and the truncation error against chi at
+    d = 9 (FP64, relative to chi = 32)."""
+    prec = a.precision
+    ds, ps, n = (5, 9, 13, 17), (0.12, 0.15, 0.17, 0.19, 0.21, 0.23), a.study_count
+    print("bench: study, %s, %d syndromes per point" % (prec, n), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    table = {}
+    for d in ds:
+        row = {}
+        for i, p in enumerate(ps):
+            rates = synth.depolarizing(d, p)
+            smp = synth.sample(d, rates, n, seed=6000 + 100 * d + i)
+            _, _, cls = tn.decode(torch.from_numpy(smp["syndromes"]).to(dev), torch.from_numpy(rates).to(dev), d,
+                                  32, prec)
+            e = float((cls.cpu().numpy() != smp["true_class"]).mean())
+            row["%.2f" % p] = {"ler": e, "stderr": float(np.sqrt(max(e * (1 - e), 1e-12) / n))}
+        table["d=%d" % d] = row
+        print("bench: d=%d done" % d, file=sys.stderr, flush=True)
+    t_ler = time.perf_counter() - t0
+    d, p, m = 9, 0.17, 1024
+    rates = synth.depolarizing(d, p)
+    smp = synth.sample(d, rates, m, seed=6900)
+    syn, rt = torch.from_numpy(smp["syndromes"]).to(dev), torch.from_numpy(rates).to(dev)
+    ref_logp = tn.decode(syn, rt, d, 32, "fp64")[1].cpu().numpy()
+    conv = {}
+    for chi in (2, 4, 8, 16):
+        _, lp, cls = tn.decode(syn, rt, d, chi, "fp64")
+        dl = np.abs(lp.cpu().numpy() - ref_logp)
+        conv["chi=%d" % chi] = {"mean_abs_dlogp": float(dl.mean()), "max_abs_dlogp": float(dl.max()),
+                                "ler": float((cls.cpu().numpy() != smp["true_class"]).mean())}
+    out = {
+        "metric": "logical error rate vs p and d (chi=32), truncation error vs chi at d=9",
+        "value": sum(len(ps) * n for _ in ds) / t_ler, "unit": "syndromes/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": t_ler * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
+        "config": {"workload": "depolarizing p in %s, d in %s, %d syndromes per point, chi=32; chi sweep at d=9 "
+                               "p=0.17 on %d syndromes" % (list(ps), list(ds), n, m), "precision": prec},
+        "logical_error_rate": table,
+        "chi_convergence_vs_chi32_fp64": conv,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -222,6 +269,9 @@ def main():
         return
     if a.workload == "fit":
         bench_fit(a, torch, tn, synth, dev)
+        return
+    if a.workload == "study":
+        bench_study(a, torch, tn, synth, dev)
         return
     if a.workload == "c3":
         rates = synth.depolarizing(D, P)

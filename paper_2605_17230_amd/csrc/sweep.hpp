@@ -344,13 +344,31 @@ __device__ void lq_form_q(Real* X, int m, int n, int ld, const Real* tau, Real* 
 // vb + (i & 1) * 16 NPL, so the row update loads it with no bounds test.  The
 // owner of row i + 1 builds the next reflector as soon as it has updated that
 // row: one barrier per step.  vb: LDS scratch of 32 NPL.
-constexpr int LQR_RPG = 2, LQR_NPL = 16;
-__device__ inline bool lq_regs_fit(int m, int n) { return m <= LQR_RPG * (NT / 16) && n <= LQR_NPL * 16; }
+// lq_rpg: rows per lane group: 2 with 512 threads; with 256 threads 4 for FP32
+// factorisations (64-row matrices in registers, as in the 512-thread build)
+// and 2 for FP64 ones (four rows of doubles would halve the waves per SIMD).
+constexpr int LQR_NPL = 16;
+template <typename Real>
+constexpr int lq_rpg() {
+  return NT >= 512 ? 2 : (sizeof(Real) == 4 ? 4 : 2);
+}
+template <typename Real>
+__device__ inline bool lq_regs_fit(int m, int n) {
+  return m <= lq_rpg<Real>() * (NT / 16) && n <= LQR_NPL * 16;
+}
+// Row held in slot j by lane group g in the explicit-Q builder: slots pair a
+// row with its mirror (g and 2 NG - 1 - g, then 2 NG + g and 4 NG - 1 - g), so
+// every group's rows need the same number of reflector steps in total.
+__device__ inline int lq_q_row(int j, int g, int ng) {
+  const int base = 2 * ng * (j >> 1);
+  return (j & 1) ? base + 2 * ng - 1 - g : base + g;
+}
 
 // NPL: columns per lane held in registers (n <= 16 NPL); instantiated for 8
 // and 16 so that 128-column matrices do not run 256-column loops.
 template <typename Real, int NPL = LQR_NPL>
 __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* diag, double* red, Real* vb) {
+  constexpr int LQR_RPG = lq_rpg<Real>();
   const int k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
   constexpr int NG = NT / 16;
@@ -440,7 +458,7 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
 // Register-resident explicit Q after lq_factor (k = min(m, n) <= 64): row r
 // of Q = [I_k 0] H_{k-1} ... H_0 is e_r - tau_r v_r pushed through
 // H_{r-1}, ..., H_0, which involves no other row of Q, so each lane group
-// builds its rows (r and 2*32-1-r, balancing the step counts) with no barrier,
+// builds its rows (lq_q_row: mirrored pairs, balancing the step counts) with no barrier,
 // reading the reflectors from X.  The strictly lower part of X (L, already
 // copied out by the caller) is first overwritten with the zeros and the
 // diagonal with the ones of the reflectors, so the loop reads rows with no
@@ -448,6 +466,7 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
 // One barrier before the rows are stored.
 template <typename Real, int NPL, bool FULL>
 __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
+  constexpr int LQR_RPG = lq_rpg<Real>();
   const int k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
   constexpr int NG = NT / 16;
@@ -458,7 +477,7 @@ __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
   Real q[LQR_RPG][NPL];
 #pragma unroll
   for (int j = 0; j < LQR_RPG; ++j) {
-    const int r = j == 0 ? grp : 2 * NG - 1 - grp;
+    const int r = lq_q_row(j, grp, NG);
     if (r >= k) continue;
     {
       const Real t = tau[r];
@@ -490,7 +509,7 @@ __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < LQR_RPG; ++j) {
-    const int r = j == 0 ? grp : 2 * NG - 1 - grp;
+    const int r = lq_q_row(j, grp, NG);
     if (r >= k) continue;
 #pragma unroll
     for (int c = 0; c < NPL; ++c) {
@@ -504,7 +523,7 @@ __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
 // Dispatch: registers when the matrix fits, else the LDS-resident version.
 template <typename Real>
 __device__ inline void lq_factor_any(Real* X, int m, int n, int ld, Real* tau, Real* diag, double* red, Real* vb) {
-  if (lq_regs_fit(m, n)) {
+  if (lq_regs_fit<Real>(m, n)) {
     if (n <= 128) lq_factor_regs<Real, 8>(X, m, n, ld, tau, diag, red, vb);
     else lq_factor_regs<Real, 16>(X, m, n, ld, tau, diag, red, vb);
   } else {
@@ -513,7 +532,7 @@ __device__ inline void lq_factor_any(Real* X, int m, int n, int ld, Real* tau, R
 }
 template <typename Real>
 __device__ inline void lq_form_q_any(Real* X, int m, int n, int ld, const Real* tau, Real* v) {
-  if (lq_regs_fit(m, n)) {
+  if (lq_regs_fit<Real>(m, n)) {
     if (n == 128) lq_form_q_regs<Real, 8, true>(X, m, n, ld, tau);
     else if (n == 256) lq_form_q_regs<Real, 16, true>(X, m, n, ld, tau);
     else if (n < 128) lq_form_q_regs<Real, 8, false>(X, m, n, ld, tau);

@@ -320,12 +320,16 @@ int validate(const tn_segment* segs, int32_t nseg) {
   return TN_OK;
 }
 
-// Plans whose site matrices have at most 32 rows (chi <= 16 with a bond-2
+// Plans whose site matrices have at most 64 rows (chi <= 32 with a bond-2
 // MPO) and at most 256 columns run on the 256-thread build of the forward
-// kernel when at least two of its work-groups fit a CU (LDS and registers).
+// kernel when at least two of its work-groups fit a CU (LDS and registers):
+// in practice chi <= 24, the larger plans need more than half the LDS.
 constexpr int kSmallNT = 256;
 bool small_plan(const PlanHeader& h, int precision) {
-  if (h.max_m > 2 * (kSmallNT / 16) || h.max_n > 256 || h.max_bond > kSmallNT) return false;
+  // rows the 256-thread build keeps in registers: 4 per 16-lane group with
+  // FP32 factorisations, 2 with FP64 ones
+  const int rpg = fac_bytes(precision) == 4 ? 4 : 2;
+  if (h.max_m > rpg * (kSmallNT / 16) || h.max_n > 256 || h.max_bond > kSmallNT) return false;
   const int lb = lds_layout(h, real_bytes(precision), fac_bytes(precision)).bytes;
   if (lb > kLdsPerCU / 2 - 256) return false;
   return tnmld_small::small_wgs_per_cu(precision, lb) >= 2;
@@ -406,8 +410,9 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
     if (L.small) {
       const int ws = tnmld_small::small_wgs_per_cu(L.precision, lb);
       w = std::min(kLdsPerCU / (lb + 256), ws > 0 ? ws : 1);
+    } else if (L.nwg > 0) {
+      w = std::min(w, L.nwg);  // tuned work-groups per CU (tuned for the 512-thread build)
     }
-    if (L.nwg > 0) w = std::min(w, L.nwg);
     if (w < 1) return fail(TN_EUNSUPPORTED, "LDS of the merged plans exceeds one CU");
     L.nwg = w * di.cus;
     *nwg = std::max(*nwg, L.nwg);

@@ -94,7 +94,7 @@ __device__ inline Work<Real, Fac> carve(uint8_t* smem, const LdsLayout& lay, int
   w.dred = reinterpret_cast<double*>(smem + lay.red);
   w.nrm = reinterpret_cast<double*>(smem + lay.nrm);
   w.Wv = reinterpret_cast<Real*>(smem + lay.W);
-  w.Aj = reinterpret_cast<Real*>(smem + lay.Aj);
+  w.Aj = lay.Aj < 0 ? nullptr : reinterpret_cast<Real*>(smem + lay.Aj);
   w.T = reinterpret_cast<Real*>(smem + lay.T);
   w.L = reinterpret_cast<Real*>(smem + lay.L);
   w.C = reinterpret_cast<Real*>(smem + lay.C);
@@ -205,7 +205,9 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
         Wv[tid] = v;
       }
       Real* g = scr + region[J];
-      for (int e = tid; e < Dl * qi * Dr; e += NT) Aj[e] = g[e];
+      const Real* As = Aj ? Aj : g;  // LDS copy, or the site region itself (its L2 lines)
+      if (Aj)
+        for (int e = tid; e < Dl * qi * Dr; e += NT) Aj[e] = g[e];
       __syncthreads();
       for (int so = 0; so < qo; ++so) {
         // T[(l,a)][(r,b)] = sum_si Aj[l][si][r] W[a][si][so][b]
@@ -214,7 +216,7 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
           const int l = A == 2 ? la >> 1 : la, a = la & (A - 1), r = B == 2 ? rb >> 1 : rb, bb = rb & (B - 1);
           Real acc = 0;
           for (int si = 0; si < qi; ++si)
-            acc += Aj[(l * qi + si) * Dr + r] * Wv[((a * qi + si) * qo + so) * B + bb];
+            acc += As[(l * qi + si) * Dr + r] * Wv[((a * qi + si) * qo + so) * B + bb];
           T[la * RB + rb] = acc;
         });
         __syncthreads();

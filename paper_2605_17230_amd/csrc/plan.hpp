@@ -124,10 +124,14 @@ struct LdsLayout {
 
 inline int32_t pad64b(int64_t x) { return (int32_t)((x + 63) / 64 * 64); }
 
-inline LdsLayout lds_layout(const PlanHeader& h, int rb, int fb) {
+// aj_global: the MPO step reads the input site tensor from its scratch region
+// instead of an LDS copy (o.Aj = -1), to fit two work-groups of the 256-thread
+// build in a CU.
+inline LdsLayout lds_layout(const PlanHeader& h, int rb, int fb, bool aj_global = false) {
   LdsLayout o{};
   int32_t p = 0;
-  o.Aj = p; p += pad64b((int64_t)h.max_Aj * rb);
+  o.Aj = aj_global ? -1 : p;
+  if (!aj_global) p += pad64b((int64_t)h.max_Aj * rb);
   o.T = p; p += pad64b((int64_t)h.max_T * rb);
   o.X = p; p += pad64b((int64_t)h.max_X * fb);
   o.L = p; p += pad64b((int64_t)h.max_L * rb);

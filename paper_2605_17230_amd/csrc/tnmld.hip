@@ -330,15 +330,20 @@ bool small_plan(const PlanHeader& h, int precision) {
   // FP32 factorisations, 2 with FP64 ones
   const int rpg = fac_bytes(precision) == 4 ? 4 : 2;
   if (h.max_m > rpg * (kSmallNT / 16) || h.max_n > 256 || h.max_bond > kSmallNT) return false;
-  const int lb = lds_layout(h, real_bytes(precision), fac_bytes(precision)).bytes;
-  if (lb > kLdsPerCU / 2 - 256) return false;
+  // half the LDS of a CU; if the input site's LDS copy is what does not fit,
+  // the MPO step reads it from the site region instead
+  const int limit = kLdsPerCU / 2 - 256;
+  int lb = lds_layout(h, real_bytes(precision), fac_bytes(precision)).bytes;
+  if (lb > limit) lb = lds_layout(h, real_bytes(precision), fac_bytes(precision), true).bytes;
+  if (lb > limit) return false;
   return tnmld_small::small_wgs_per_cu(precision, lb) >= 2;
 }
 
 constexpr int kMaxLaunches = 2 * (TN_FP32_PLAIN + 1);  // one per precision and size class
 
 struct Launch {
-  bool small;  // 256-thread build
+  bool small;      // 256-thread build
+  bool aj_global;  // small launch whose MPO step reads the input site from its region (LDS)
   int precision;
   JobTable jt;  // forward items are syndromes
   PlanHeader merged;
@@ -400,12 +405,13 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
       if (tw > 0) L.nwg = L.nwg ? std::min(L.nwg, tw) : tw;  // per-CU count for now
     }
     L.jt.nitems = items;
+    L.aj_global = small && lds_layout(L.merged, real_bytes(prec), fac_bytes(prec)).bytes > kLdsPerCU / 2 - 256;
     if (L.jt.n > 0) out->push_back(L);
   }
   size_t bytes = align_up(sizeof(unsigned long long) * kMaxLaunches);
   for (auto& L : *out) {
     if (L.merged.max_bond > NT) return fail(TN_EUNSUPPORTED, "bond dimension above the work-group size");
-    const int lb = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision)).bytes;
+    const int lb = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision), L.aj_global).bytes;
     int w = wgs_for(lb, fwd_kernel_of(L.precision));
     if (L.small) {
       const int ws = tnmld_small::small_wgs_per_cu(L.precision, lb);
@@ -455,7 +461,7 @@ int run_forward(const tn_segment* segs, int32_t nseg, void* workspace, size_t ws
     char* scr = base + off;
     off += (size_t)L.nwg * align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
     if (L.small) {
-      const LdsLayout lay = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision));
+      const LdsLayout lay = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision), L.aj_global);
       const int64_t stride = (int64_t)align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
       if (tnmld_small::launch_fwd_small(L.precision, &L.jt, counter, scr, stride, L.scratch_elems, &lay, lay.bytes,
                                         L.nwg, st) != 0)

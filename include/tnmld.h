@@ -94,8 +94,10 @@ size_t tn_workspace_size(const tn_segment* segs, int32_t nseg, int32_t with_back
 
 /* log Z_l(s) for every syndrome of every segment (Sec. 2.3 eq. "coset_prob",
  * contracted by boundary MPS as in Sec. 3.2.1), written to out_logz; also
- * out_logp when non-NULL.  One persistent launch per precision drains a work
- * queue of (syndrome, coset) items across all segments, largest d first.
+ * out_logp when non-NULL.  Persistent launches (one per precision and size
+ * class) drain a work queue of syndromes across all segments, largest d
+ * first; a syndrome's four cosets share the rows before the logical
+ * representatives.
  * segs: HOST array of nseg <= TN_MAX_SEGMENTS descriptors.  workspace: device,
  * ws_bytes >= tn_workspace_size(segs, nseg, 0), caller-owned, reused freely
  * after the call completes on `stream`. */
@@ -111,9 +113,10 @@ int tn_decode_batch(const tn_segment* segs, int32_t nseg, double tie_tol, void* 
 /* Gradient of the weighted log-likelihood  sum_b grad_logp[b] * log P(s_b)
  * (the per-syndrome term of the paper's eq. "dmle_loss") with respect to
  * theta_{q,P} = ln p_{q,P}, P in {X, Y, Z}, p_I = 1 - p_X - p_Y - p_Z.
- * Contracts each (syndrome, coset) forward with row checkpoints, recomputes
- * each segment of rows from its checkpoint, sweeps a second boundary MPS up
- * from the bottom, and contracts the environment of every qubit tensor.
+ * Contracts each syndrome's cosets forward with row checkpoints (the rows
+ * common to the four cosets once), recomputes each segment of rows from its
+ * checkpoint, sweeps a second boundary MPS up from the bottom, and contracts
+ * the environment of every qubit tensor.
  * grad_logp[s]: device [count] of segment s; grad_log_rates[s]: device
  * [n_models][d*d][3], ACCUMULATED (+=) in FP64 by a deterministic reduction.
  * forward_done = 0: the call first runs the forward pass and writes out_logz /

@@ -185,16 +185,21 @@ __device__ void row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
   }
 }
 
-// Backward of one (syndrome b, coset mlog): adds weight * d log Z / d theta
-// to part (FP64, [n][3]) where weight = grad_logp[b] * P(l|s).  Scratch
-// layout (in Real elements): top regions | bottom regions | K-row checkpoints
-// | segment states | environments | three temporaries.  Collective.
+// Backward of syndrome b over its four cosets: adds, for each coset mlog,
+// weight_mlog * d log Z_mlog / d theta to part (FP64, [n][3]) where
+// weight = grad_logp[b] * P(l|s).  The rows before H->shared_rows are the same
+// for the four cosets (as in the forward pass), so the top-down sweep over them
+// and its checkpoints are computed once and the MPS after them is kept in
+// snap; each coset continues from it.  Scratch layout (in Real elements): top
+// regions | bottom regions | K-row checkpoints | segment states |
+// environments | three temporaries | snapshot.  Collective.
 template <typename Real, typename Fac, int GM>
-__device__ void adjoint_one(const JobDev& job, int64_t b, int mlog, uint8_t* smem, const LdsLayout& lay, Real* scr,
-                            int kseg, double* part) {
+__device__ void adjoint_syndrome(const JobDev& job, int64_t b, uint8_t* smem, const LdsLayout& lay, Real* scr,
+                                 int kseg, double* part) {
   const uint8_t* plan = job.plan;
   const PlanHeader* H = reinterpret_cast<const PlanHeader*>(plan);
   const int n = H->n, m = H->m, nsite = H->nsite, nstep = H->nstep;
+  const int S = H->shared_rows;
   const SiteStep* steps = reinterpret_cast<const SiteStep*>(plan + H->steps_ofs);
   const SiteStep* bsteps = reinterpret_cast<const SiteStep*>(plan + H->bu_steps_ofs);
   const uint8_t* codes = plan + H->codes_ofs;
@@ -203,18 +208,22 @@ __device__ void adjoint_one(const JobDev& job, int64_t b, int mlog, uint8_t* sme
   const int16_t* fin = reinterpret_cast<const int16_t*>(plan + H->final_ofs);
   __shared__ int s_flags[2];
   __shared__ int s_label;
-  __shared__ double s_weight;
+  __shared__ double s_weight[4];
   Work<Real, Fac> w = carve<Real, Fac>(smem, lay, s_flags);
   const int model = job.model_index ? job.model_index[b] : 0;
   const double* rates = job.rates + (int64_t)model * n * 3;
-  const int label = prep_reference(H, checks, job.syn + b * m, mlog, w.syn, w.fbits, &s_label);
-  if (threadIdx.x == 0) {
-    const double lz = job.logz[b * 4 + label], lp = job.logp[b], gp = job.gradp[b];
-    s_weight = (lz > -INFINITY && lp > -INFINITY && gp != 0.0) ? gp * exp(lz - lp) : 0.0;
+  const uint8_t* syn = job.syn + b * m;
+  int first = -1;
+  for (int mlog = 0; mlog < 4; ++mlog) {
+    const int label = prep_reference(H, checks, syn, mlog, w.syn, w.fbits, &s_label);
+    if (threadIdx.x == 0) {
+      const double lz = job.logz[b * 4 + label], lp = job.logp[b], gp = job.gradp[b];
+      s_weight[mlog] = (lz > -INFINITY && lp > -INFINITY && gp != 0.0) ? gp * exp(lz - lp) : 0.0;
+    }
+    __syncthreads();
+    if (first < 0 && s_weight[mlog] != 0.0) first = mlog;
   }
-  __syncthreads();
-  const double weight = s_weight;
-  if (weight == 0.0) return;
+  if (first < 0) return;
 
   const int64_t se = H->scratch_elems, me = H->mps_elems;
   const int ncp = (nstep + kseg - 1) / kseg;
@@ -226,6 +235,7 @@ __device__ void adjoint_one(const JobDev& job, int64_t b, int mlog, uint8_t* sme
   Real* P1 = env + H->env_elems;
   Real* P2 = P1 + H->tmp_elems;
   Real* P3 = P2 + H->tmp_elems;
+  Real* snap = P3 + H->tmp_elems;
   double* pm = part + (int64_t)model * n * 3;
   auto in_dims = [&](const SiteStep* row) {
     return [row](int J, int& Dl, int& q, int& Dr) {
@@ -234,41 +244,62 @@ __device__ void adjoint_one(const JobDev& job, int64_t b, int mlog, uint8_t* sme
       Dr = row[J].Dr_old;
     };
   };
-  // --- top-down with checkpoints every kseg rows ----------------------------
+  // --- shared rows: top-down once, with their checkpoints ------------------
+  // (the reference error of any coset agrees on these rows)
+  prep_reference(H, checks, syn, first, w.syn, w.fbits, &s_label);
   mps_ones(top, region, plan + H->init_qi_ofs, nsite);
   double logscale = 0.0;
-  for (int u = 0; u < nstep; ++u) {
+  for (int u = 0; u < S; ++u) {
     const SiteStep* row = steps + (int64_t)u * nsite;
     if (u % kseg == 0) mps_pack(top, region, nsite, in_dims(row), cps + (int64_t)(u / kseg) * me, false, top);
     if (!row_step_outlined<Real, Fac, GM>(row, nsite, codes, rates, top, region, w, logscale)) return;
   }
-  // --- bottom-up, recomputing each segment of top states -------------------
-  {
-    // all-ones over the final frontier
-    for (int J = 0; J < nsite; ++J)
+  if (S > 0) mps_pack(top, region, nsite, in_dims(steps + (int64_t)S * nsite), snap, false, top);
+  const double logscale_s = logscale;
+
+  for (int mlog = first; mlog < 4; ++mlog) {
+    const double weight = s_weight[mlog];
+    if (weight == 0.0) continue;
+    prep_reference(H, checks, syn, mlog, w.syn, w.fbits, &s_label);
+    // --- the coset's own rows: top-down with checkpoints every kseg rows ----
+    if (S > 0) mps_pack(top, region, nsite, in_dims(steps + (int64_t)S * nsite), snap, true, top);
+    else mps_ones(top, region, plan + H->init_qi_ofs, nsite);
+    logscale = logscale_s;
+    bool alive = true;
+    for (int u = S; u < nstep && alive; ++u) {
+      const SiteStep* row = steps + (int64_t)u * nsite;
+      if (u % kseg == 0) mps_pack(top, region, nsite, in_dims(row), cps + (int64_t)(u / kseg) * me, false, top);
+      alive = row_step_outlined<Real, Fac, GM>(row, nsite, codes, rates, top, region, w, logscale);
+    }
+    if (!alive) continue;
+    // --- bottom-up, recomputing each segment of top states -----------------
+    for (int J = 0; J < nsite; ++J)  // all-ones over the final frontier
       for (int e = threadIdx.x; e < fin[3 * J + 1]; e += NT) bot[region[J] + e] = Real(1);
     __syncthreads();
-  }
-  int cur = -1;
-  double bscale = 0.0;
-  for (int u = nstep - 1; u >= 0; --u) {
-    const int c = u / kseg;
-    if (c != cur) {
-      const int t0 = c * kseg, t1 = (t0 + kseg < nstep ? t0 + kseg : nstep);
-      mps_pack(top, region, nsite, in_dims(steps + (int64_t)t0 * nsite), cps + (int64_t)c * me, true, top);
-      mps_pack(top, region, nsite, in_dims(steps + (int64_t)t0 * nsite), seg, false, top);
-      for (int t = t0; t + 1 < t1; ++t) {
-        if (!row_step_outlined<Real, Fac, GM>(steps + (int64_t)t * nsite, nsite, codes, rates, top, region, w, logscale)) return;
-        mps_pack(top, region, nsite, in_dims(steps + (int64_t)(t + 1) * nsite), seg + (int64_t)(t + 1 - t0) * me, false,
-                 top);
+    int cur = -1;
+    double bscale = 0.0;
+    for (int u = nstep - 1; u >= 0 && alive; --u) {
+      const int c = u / kseg;
+      if (c != cur) {
+        const int t0 = c * kseg, t1 = (t0 + kseg < nstep ? t0 + kseg : nstep);
+        mps_pack(top, region, nsite, in_dims(steps + (int64_t)t0 * nsite), cps + (int64_t)c * me, true, top);
+        mps_pack(top, region, nsite, in_dims(steps + (int64_t)t0 * nsite), seg, false, top);
+        for (int t = t0; t + 1 < t1 && alive; ++t) {
+          alive = row_step_outlined<Real, Fac, GM>(steps + (int64_t)t * nsite, nsite, codes, rates, top, region, w,
+                                                   logscale);
+          if (alive)
+            mps_pack(top, region, nsite, in_dims(steps + (int64_t)(t + 1) * nsite), seg + (int64_t)(t + 1 - t0) * me,
+                     false, top);
+        }
+        cur = c;
       }
-      cur = c;
+      if (!alive) break;
+      const SiteStep* frow = steps + (int64_t)u * nsite;
+      const SiteStep* brow = bsteps + (int64_t)(nstep - 1 - u) * nsite;
+      row_gradient<Real>(frow, brow, nsite, codes, rates, w.fbits, seg + (int64_t)(u - c * kseg) * me, bot, region,
+                         env, P1, P2, P3, w.Wv, weight, pm);
+      if (u > 0) alive = row_step_outlined<Real, Fac, GM>(brow, nsite, codes, rates, bot, region, w, bscale);
     }
-    const SiteStep* frow = steps + (int64_t)u * nsite;
-    const SiteStep* brow = bsteps + (int64_t)(nstep - 1 - u) * nsite;
-    row_gradient<Real>(frow, brow, nsite, codes, rates, w.fbits, seg + (int64_t)(u - c * kseg) * me, bot, region, env, P1,
-                       P2, P3, w.Wv, weight, pm);
-    if (u > 0 && !row_step_outlined<Real, Fac, GM>(brow, nsite, codes, rates, bot, region, w, bscale)) return;
   }
 }
 

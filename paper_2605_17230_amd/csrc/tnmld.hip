@@ -82,8 +82,7 @@ __global__ __launch_bounds__(NT) void bwd_kernel(JobTable jt, char* scratch, int
     int jb = 0;
     while (jb + 1 < jt.n && jt.j[jb + 1].item_begin <= item) ++jb;
     const JobDev& job = jt.j[jb];
-    const int64_t local = item - job.item_begin;
-    adjoint_one<Real, Fac, GM>(job, local >> 2, (int)(local & 3), smem, lay, scr, kseg, mypart + job.part_ofs);
+    adjoint_syndrome<Real, Fac, GM>(job, item - job.item_begin, smem, lay, scr, kseg, mypart + job.part_ofs);
     __syncthreads();
   }
 }
@@ -515,11 +514,11 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
   bl->jt = L.jt;
   bl->merged = L.merged;
   {
-    // backward items are (syndrome, coset) pairs
+    // backward items are syndromes (the four cosets of one in a work-group)
     int64_t items = 0;
     for (int i = 0; i < bl->jt.n; ++i) {
       bl->jt.j[i].item_begin = items;
-      items += 4 * bl->jt.j[i].count;
+      items += bl->jt.j[i].count;
     }
     bl->jt.nitems = items;
   }
@@ -547,8 +546,8 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
     const int ks = (int)std::ceil(std::sqrt((double)H->nstep));
     const int ncp = (H->nstep + ks - 1) / ks;
     nstep_max = std::max(nstep_max, H->nstep);
-    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems + (int64_t)(ncp + ks) * H->mps_elems + H->env_elems +
-                                               3 * H->tmp_elems);
+    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems + (int64_t)(ncp + ks + 1) * H->mps_elems +
+                                               H->env_elems + 3 * H->tmp_elems);
     ++ji;
   }
   bl->kseg = (int)std::ceil(std::sqrt((double)nstep_max));
@@ -562,7 +561,8 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
         if (kv.second->dev == bl->jt.j[i].plan) H = &kv.second->plan.h;
     }
     const int ncp = (H->nstep + bl->kseg - 1) / bl->kseg;
-    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems + (int64_t)(ncp + bl->kseg) * H->mps_elems +
+    // checkpoints, segment states and the snapshot after the shared rows
+    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems + (int64_t)(ncp + bl->kseg + 1) * H->mps_elems +
                                                H->env_elems + 3 * H->tmp_elems);
   }
   const int lb = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision)).bytes;

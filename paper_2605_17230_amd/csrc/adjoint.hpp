@@ -190,9 +190,12 @@ __device__ void row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
 // weight = grad_logp[b] * P(l|s).  The rows before H->shared_rows are the same
 // for the four cosets (as in the forward pass), so the top-down sweep over them
 // and its checkpoints are computed once and the MPS after them is kept in
-// snap; each coset continues from it.  Scratch layout (in Real elements): top
-// regions | bottom regions | K-row checkpoints | segment states |
-// environments | three temporaries | snapshot.  Collective.
+// snap; each coset continues from it.  Segments of kseg rows that lie within
+// the shared rows recompute the same top states for every coset: they are
+// kept from the first coset that needs them.  Scratch layout (in Real
+// elements): top regions | bottom regions | K-row checkpoints | segment
+// states | environments | three temporaries | snapshot | shared segment
+// states (S / kseg segments of kseg states).  Collective.
 template <typename Real, typename Fac, int GM>
 __device__ void adjoint_syndrome(const JobDev& job, int64_t b, uint8_t* smem, const LdsLayout& lay, Real* scr,
                                  int kseg, double* part) {
@@ -236,6 +239,9 @@ __device__ void adjoint_syndrome(const JobDev& job, int64_t b, uint8_t* smem, co
   Real* P2 = P1 + H->tmp_elems;
   Real* P3 = P2 + H->tmp_elems;
   Real* snap = P3 + H->tmp_elems;
+  Real* shseg = snap + me;
+  const int nshc = S / kseg;  // segments entirely within the shared rows
+  unsigned shdone = 0;        // bit c: shared segment c recomputed
   double* pm = part + (int64_t)model * n * 3;
   auto in_dims = [&](const SiteStep* row) {
     return [row](int J, int& Dl, int& q, int& Dr) {
@@ -278,25 +284,31 @@ __device__ void adjoint_syndrome(const JobDev& job, int64_t b, uint8_t* smem, co
     __syncthreads();
     int cur = -1;
     double bscale = 0.0;
+    Real* sbase = seg;
     for (int u = nstep - 1; u >= 0 && alive; --u) {
       const int c = u / kseg;
       if (c != cur) {
-        const int t0 = c * kseg, t1 = (t0 + kseg < nstep ? t0 + kseg : nstep);
-        mps_pack(top, region, nsite, in_dims(steps + (int64_t)t0 * nsite), cps + (int64_t)c * me, true, top);
-        mps_pack(top, region, nsite, in_dims(steps + (int64_t)t0 * nsite), seg, false, top);
-        for (int t = t0; t + 1 < t1 && alive; ++t) {
-          alive = row_step_outlined<Real, Fac, GM>(steps + (int64_t)t * nsite, nsite, codes, rates, top, region, w,
-                                                   logscale);
-          if (alive)
-            mps_pack(top, region, nsite, in_dims(steps + (int64_t)(t + 1) * nsite), seg + (int64_t)(t + 1 - t0) * me,
-                     false, top);
+        const bool shared = c < nshc;
+        sbase = shared ? shseg + (int64_t)c * kseg * me : seg;
+        if (!(shared && (shdone >> c & 1u))) {
+          const int t0 = c * kseg, t1 = (t0 + kseg < nstep ? t0 + kseg : nstep);
+          mps_pack(top, region, nsite, in_dims(steps + (int64_t)t0 * nsite), cps + (int64_t)c * me, true, top);
+          mps_pack(top, region, nsite, in_dims(steps + (int64_t)t0 * nsite), sbase, false, top);
+          for (int t = t0; t + 1 < t1 && alive; ++t) {
+            alive = row_step_outlined<Real, Fac, GM>(steps + (int64_t)t * nsite, nsite, codes, rates, top, region, w,
+                                                     logscale);
+            if (alive)
+              mps_pack(top, region, nsite, in_dims(steps + (int64_t)(t + 1) * nsite),
+                       sbase + (int64_t)(t + 1 - t0) * me, false, top);
+          }
+          if (shared && alive) shdone |= 1u << c;
         }
         cur = c;
       }
       if (!alive) break;
       const SiteStep* frow = steps + (int64_t)u * nsite;
       const SiteStep* brow = bsteps + (int64_t)(nstep - 1 - u) * nsite;
-      row_gradient<Real>(frow, brow, nsite, codes, rates, w.fbits, seg + (int64_t)(u - c * kseg) * me, bot, region,
+      row_gradient<Real>(frow, brow, nsite, codes, rates, w.fbits, sbase + (int64_t)(u - c * kseg) * me, bot, region,
                          env, P1, P2, P3, w.Wv, weight, pm);
       if (u > 0) alive = row_step_outlined<Real, Fac, GM>(brow, nsite, codes, rates, bot, region, w, bscale);
     }

@@ -546,8 +546,8 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
     const int ks = (int)std::ceil(std::sqrt((double)H->nstep));
     const int ncp = (H->nstep + ks - 1) / ks;
     nstep_max = std::max(nstep_max, H->nstep);
-    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems + (int64_t)(ncp + ks + 1) * H->mps_elems +
-                                               H->env_elems + 3 * H->tmp_elems);
+    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems + (int64_t)(ncp + ks + 1 + H->shared_rows) *
+                                               H->mps_elems + H->env_elems + 3 * H->tmp_elems);
     ++ji;
   }
   bl->kseg = (int)std::ceil(std::sqrt((double)nstep_max));
@@ -561,8 +561,11 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
         if (kv.second->dev == bl->jt.j[i].plan) H = &kv.second->plan.h;
     }
     const int ncp = (H->nstep + bl->kseg - 1) / bl->kseg;
-    // checkpoints, segment states and the snapshot after the shared rows
-    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems + (int64_t)(ncp + bl->kseg + 1) * H->mps_elems +
+    // checkpoints, segment states, the snapshot after the shared rows and the
+    // kept states of the segments within them
+    const int nshc = H->shared_rows / bl->kseg;
+    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems +
+                                               (int64_t)(ncp + bl->kseg + 1 + nshc * bl->kseg) * H->mps_elems +
                                                H->env_elems + 3 * H->tmp_elems);
   }
   const int lb = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision)).bytes;

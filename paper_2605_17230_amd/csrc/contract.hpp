@@ -178,11 +178,23 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
   double* dred = w.dred;
   Real *Wv = w.Wv, *Aj = w.Aj, *T = w.T, *L = w.L, *C = w.C;
   Fac *X = w.X, *tau = w.tau, *diag = w.diag, *vtmp = w.vtmp, *Mm = w.Mm, *Vv = w.Vv, *Lt = w.Lt, *sig = w.sig;
+  // BF16 form: T and L reach the T.L GEMM as bf16 hi/lo planes, split once
+  // when they are written (T row-major, L transposed; rows padded to 8)
+#ifndef TNMLD_EMU
+  constexpr bool PL = GM != GEMM_VALU && sizeof(Real) == 4;
+#else
+  constexpr bool PL = false;
+#endif
   if (tid == 0) w.s_dead[0] = 0;
   __syncthreads();
   do {
     // --- right-to-left: MPO apply + LQ --------------------------------------
-    if (tid == 0) L[0] = Real(1);
+    if constexpr (PL) {  // 1 x 1 carry = 1: one row of 8 (bf16 one = 0x3f80)
+      uint16_t* Lh = reinterpret_cast<uint16_t*>(L);
+      if (tid < 16) Lh[tid] = tid == 0 ? uint16_t(0x3f80) : uint16_t(0);
+    } else {
+      if (tid == 0) L[0] = Real(1);
+    }
     __syncthreads();
     for (int J = nsite - 1; J >= 0; --J) {
       const SiteStep st = row[J];
@@ -209,25 +221,60 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
       if (Aj)
         for (int e = tid; e < Dl * qi * Dr; e += NT) Aj[e] = g[e];
       __syncthreads();
+      const int ldp = (RB + 7) & ~7;  // plane row length (BF16 form)
       for (int so = 0; so < qo; ++so) {
         // T[(l,a)][(r,b)] = sum_si Aj[l][si][r] W[a][si][so][b]
         // (A and B, the MPO bonds, are 1 or 2)
-        for_2d(mJ, RB, [&](int la, int rb) {
+        auto tval = [&](int la, int rb) {
           const int l = A == 2 ? la >> 1 : la, a = la & (A - 1), r = B == 2 ? rb >> 1 : rb, bb = rb & (B - 1);
           Real acc = 0;
           for (int si = 0; si < qi; ++si)
             acc += As[(l * qi + si) * Dr + r] * Wv[((a * qi + si) * qo + so) * B + bb];
-          T[la * RB + rb] = acc;
-        });
-        __syncthreads();
-        // X[:, so*kr + c] = T . L
-        contract_gemm<GM, Real>(mJ, kr, RB, T, RB, L, kr, 0, 0,
-                                [&](int i, int j, Real v) { X[i * nn + so * kr + j] = Fac(v); });
+          return acc;
+        };
+        if constexpr (PL) {
+#ifndef TNMLD_EMU
+          uint16_t* Th = reinterpret_cast<uint16_t*>(T);
+          uint16_t* Tl = Th + mJ * ldp;
+          for_2d(mJ, ldp, [&](int la, int rb) {
+            uint16_t h, l;
+            split_bf16(rb < RB ? float(tval(la, rb)) : 0.0f, h, l);
+            Th[la * ldp + rb] = h;
+            Tl[la * ldp + rb] = l;
+          });
+          __syncthreads();
+          // X[:, so*kr + c] = T . L
+          const uint16_t* Lh = reinterpret_cast<const uint16_t*>(L);
+          gemm_mfma_planes(mJ, kr, RB, Th, Tl, ldp, Lh, Lh + kr * ldp, ldp,
+                           [&](int i, int j, float v) { X[i * nn + so * kr + j] = Fac(v); });
+#endif
+        } else {
+          for_2d(mJ, RB, [&](int la, int rb) { T[la * RB + rb] = tval(la, rb); });
+          __syncthreads();
+          // X[:, so*kr + c] = T . L
+          contract_gemm<GM, Real>(mJ, kr, RB, T, RB, L, kr, 0, 0,
+                                  [&](int i, int j, Real v) { X[i * nn + so * kr + j] = Fac(v); });
+        }
         __syncthreads();
       }
       lq_factor_any<Fac>(X, mJ, nn, nn, tau, diag, dred, vtmp);
       // L (mJ x k) for the site to the left
-      for_2d(mJ, k, [&](int r, int c) { L[r * k + c] = Real(c < r ? X[r * nn + c] : (c == r ? diag[r] : Fac(0))); });
+      auto lval = [&](int r, int c) { return c < r ? X[r * nn + c] : (c == r ? diag[r] : Fac(0)); };
+      if (PL && J > 0) {
+#ifndef TNMLD_EMU
+        // as the left site's B operand: transposed, k rows of pad8(mJ)
+        const int ldw = (mJ + 7) & ~7;
+        uint16_t* Lh = reinterpret_cast<uint16_t*>(L);
+        for_2d(k, ldw, [&](int c, int r) {
+          uint16_t h, l;
+          split_bf16(r < mJ ? float(lval(r, c)) : 0.0f, h, l);
+          Lh[c * ldw + r] = h;
+          Lh[k * ldw + c * ldw + r] = l;
+        });
+#endif
+      } else {
+        for_2d(mJ, k, [&](int r, int c) { L[r * k + c] = Real(lval(r, c)); });
+      }
       __syncthreads();
       lq_form_q_any<Fac>(X, mJ, nn, nn, tau, vtmp);
       for (int e = tid; e < k * nn; e += NT) g[e] = Real(X[e]);

@@ -36,6 +36,7 @@ struct Layout {
 };
 
 inline int pauli_of(int x, int z) { return x ? (z ? 2 : 1) : (z ? 3 : 0); }
+inline int pad8(int x) { return (x + 7) / 8 * 8; }
 
 inline double qr_flops(double M, double N) {  // Householder factorisation, M >= N
   if (M < N) std::swap(M, N);
@@ -221,9 +222,9 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
       region[J] = std::max(region[J], sz);
       int rB = S.Dr_old * S.B;
       h.max_Aj = std::max(h.max_Aj, S.Dl_old * S.qi * S.Dr_old);
-      h.max_T = std::max(h.max_T, S.m * rB);
+      h.max_T = std::max(h.max_T, S.m * pad8(rB));  // rows padded for the bf16 planes
       h.max_X = std::max(h.max_X, S.m * S.qo * S.kr);
-      h.max_L = std::max({h.max_L, S.m * S.k, rB * S.kr});
+      h.max_L = std::max({h.max_L, S.m * S.k, pad8(rB) * S.kr, S.k * pad8(S.m)});
       h.max_C = std::max(h.max_C, S.Dl_new * S.k);
       h.max_M = std::max(h.max_M, (S.Dl_new * S.qo + 1) * S.kr);
       h.max_V = std::max(h.max_V, (S.kr + 1) * S.kr);
@@ -307,9 +308,9 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
         mps += std::max<int64_t>((int64_t)S.Dl_new * S.qo * S.Dr_new, (int64_t)S.Dl_old * S.qi * S.Dr_old);
         int rB = S.Dr_old * S.B;
         h.max_Aj = std::max(h.max_Aj, S.Dl_old * S.qi * S.Dr_old);
-        h.max_T = std::max(h.max_T, S.m * rB);
+        h.max_T = std::max(h.max_T, S.m * pad8(rB));  // rows padded for the bf16 planes
         h.max_X = std::max(h.max_X, S.m * S.qo * S.kr);
-        h.max_L = std::max({h.max_L, S.m * S.k, rB * S.kr});
+        h.max_L = std::max({h.max_L, S.m * S.k, pad8(rB) * S.kr, S.k * pad8(S.m)});
         h.max_C = std::max(h.max_C, S.Dl_new * S.k);
         h.max_M = std::max(h.max_M, (S.Dl_new * S.qo + 1) * S.kr);
         h.max_V = std::max(h.max_V, (S.kr + 1) * S.kr);

@@ -81,9 +81,9 @@ struct PlanHeader {  // device-visible, followed by the tables at the offsets be
   int64_t tmp_elems;      // elements of one environment temporary (adjoint)
   // maxima used to carve LDS (elements)
   int32_t max_Aj;   // Dl_old * qi * Dr_old           input site tensor
-  int32_t max_T;    // m * (Dr_old * B)               one output slice of the MPO-applied site
+  int32_t max_T;    // m * pad8(Dr_old * B)           one output slice of the MPO-applied site
   int32_t max_X;    // m * qo * kr                    LQ matrix of the right-to-left sweep
-  int32_t max_L;    // max(m * k, Dr_old * B * kr)    carry of the right-to-left sweep
+  int32_t max_L;    // max(m k, pad8(Dr_old B) kr, k pad8(m))  carry of the right-to-left sweep
   int32_t max_C;    // Dl_new * k                     carry of the left-to-right sweep
   int32_t max_M;    // (Dl_new * qo + 1) * kr         matrix to truncate (padded columns)
   int32_t max_V;    // (kr + 1) * kr                  right rotations

@@ -207,6 +207,53 @@ __device__ inline void gemm_mfma_bf16(int M, int N, int K, ALoad aload, BLoad bl
   }
 }
 
+// FP32 -> bf16 hi + lo (bits), the split of the three-product GEMMs.
+__device__ inline void split_bf16(float x, uint16_t& hi, uint16_t& lo) {
+  const __bf16 h = (__bf16)x;
+  hi = __builtin_bit_cast(uint16_t, h);
+  lo = __builtin_bit_cast(uint16_t, (__bf16)(x - (float)h));
+}
+
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ inline bf16x8_t load_bf16x8(const uint16_t* p, bool ok) {
+  u32x4_t v = {0u, 0u, 0u, 0u};
+  if (ok) v = *reinterpret_cast<const u32x4_t*>(p);
+  return __builtin_bit_cast(bf16x8_t, v);
+}
+
+// C (M x N) = A (M x K) B (K x N) on the matrix cores, from operands already
+// split into bf16 planes: A row-major (Ah, Al, leading dimension lda), B
+// stored transposed (row c of Bh, Bl holds column c of B, leading dimension
+// ldb).  lda and ldb are multiples of 8, the planes 16-byte aligned, and
+// columns K..pad8(K)-1 of both hold zeros.  Same three products and lane
+// layout as gemm_mfma_bf16, with one 16-byte load per operand and k-step.
+template <typename Store>
+__device__ inline void gemm_mfma_planes(int M, int N, int K, const uint16_t* Ah, const uint16_t* Al, int lda,
+                                        const uint16_t* Bh, const uint16_t* Bl, int ldb, Store store) {
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
+  const int lr = lane & 15, lk = (lane >> 4) * 8, K8 = (K + 7) & ~7;
+  for (int t = wave; t < tm * tn; t += NT / WAVE) {
+    const int i0 = (t / tn) << 4, j0 = (t % tn) << 4;
+    const int r = i0 + lr, c = j0 + lr;
+    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      const int kk = k0 + lk;
+      const bool oka = r < M && kk < K8, okb = c < N && kk < K8;
+      const bf16x8_t ah = load_bf16x8(Ah + r * lda + kk, oka), al = load_bf16x8(Al + r * lda + kk, oka);
+      const bf16x8_t bh = load_bf16x8(Bh + c * ldb + kk, okb), bl = load_bf16x8(Bl + c * ldb + kk, okb);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rr = i0 + (lane >> 4) * 4 + i;
+      if (rr < M && c < N) store(rr, c, acc[i]);
+    }
+  }
+}
+
 #endif  // TNMLD_EMU
 
 // Householder LQ of X (m x n, row-major, leading dimension ld), in place:

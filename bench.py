@@ -252,7 +252,7 @@ def bench_study(a, torch, tn, synth, dev):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(syndromes would shard across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
     if a.copy_calibration:

@@ -32,6 +32,7 @@ D, CHI, P, COUNT, SEED = 17, 32, 0.12, 16384, 3000
 # MI355X non-packed VALU peak: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz;
 # FP64 runs at the same rate.
 PEAK_ALU_TFLOPS = 78.6
+PEAK_MFMA_BF16_TFLOPS = 2500.0  # dense bf16 matrix peak of the MI355X
 
 
 def parse():
@@ -299,6 +300,8 @@ def main():
     # counted work as executed: per syndrome, the rows common to its four cosets once, the rest four times
     flops_per_step = sum(len(s["syndromes"]) * tn.plan_info(s["d"], s["chi"], a.precision)["flops_syndrome"]
                          for s in segs_h)
+    gemm_per_step = sum(len(s["syndromes"]) * tn.plan_info(s["d"], s["chi"], a.precision)["gemm_flops_syndrome"]
+                        for s in segs_h)
     segs = inputs(a.precision)
     print("bench: %s, %s, %d warmup + %d timed steps" % (workload, a.precision, a.warmup, a.steps),
           file=sys.stderr, flush=True)
@@ -343,6 +346,13 @@ def main():
                      "flops_per_launch": flops_per_step, "kernel": "fwd_kernel"},
         "wall_s": wall,
     }
+    if a.precision == "bf16":
+        # the GEMM-class part on the matrix cores: each product runs as three
+        # bf16 MFMA products (hi/lo split), counted once here
+        mf = gemm_per_step / (ms_step / 1e3) / 1e12
+        out["mfma"] = {"gemm_flops_per_launch": gemm_per_step, "gemm_share_of_counted": gemm_per_step / flops_per_step,
+                       "achieved": mf, "peak": PEAK_MFMA_BF16_TFLOPS, "unit": "TFLOP/s",
+                       "frac": mf / PEAK_MFMA_BF16_TFLOPS, "bf16_products_per_gemm_flop": 3}
     print("bench: timed %.1f ms per step" % ms_step, file=sys.stderr, flush=True)
     lz = [o.logz.cpu().numpy() for o in outs]
     cls = [o.cls.cpu().numpy() for o in outs]

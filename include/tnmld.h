@@ -145,6 +145,17 @@ int tn_code_stabilizers(int32_t d, int32_t* type_out, int32_t* support_out);
  * info: host array of >= 8 doubles.  Returns TN_OK or a tn_status. */
 int tn_plan_info(int32_t d, int32_t chi, int32_t precision, double* info);
 
+/* HOST helper: the GEMM-class part of the counted forward work of the plan
+ * for (d, chi, precision): the MPO-applied site times the carried factor, the
+ * carry times the right-canonical site, and on truncated bonds the orthonormal
+ * factor times the kept right singular vectors.  These are the products the
+ * BF16 form runs on the matrix cores (each as three bf16 products, counted
+ * once here); the other forms run them on the vector units.
+ * out[0] per (syndrome, coset); out[1] per syndrome as executed (rows common
+ * to the four cosets once).  out: host array of >= 2 doubles.  Returns TN_OK
+ * or a tn_status. */
+int tn_plan_gemm_flops(int32_t d, int32_t chi, int32_t precision, double* out);
+
 /* HOST helper: launch shape for (d, chi, precision) used by later calls in
  * this process: group = lattice columns per MPS site (1 or 2; 0 = automatic),
  * wg_per_cu = persistent work-groups per compute unit (1 or 2; 0 = as many as

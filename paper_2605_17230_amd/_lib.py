@@ -58,6 +58,8 @@ def lib():
         L.tn_code_stabilizers.argtypes = [I32, P, P]
         L.tn_plan_info.restype = ctypes.c_int
         L.tn_plan_info.argtypes = [I32, I32, I32, ctypes.POINTER(D)]
+        L.tn_plan_gemm_flops.restype = ctypes.c_int
+        L.tn_plan_gemm_flops.argtypes = [I32, I32, I32, ctypes.POINTER(D)]
         L.tn_set_tuning.restype = ctypes.c_int
         L.tn_set_tuning.argtypes = [I32, I32, I32, I32, I32]
         L.tn_last_error.restype = ctypes.c_char_p

@@ -195,8 +195,11 @@ def log_posterior(log_rates, syndromes, d, chi, precision="fp32", model_index=No
 def plan_info(d, chi, precision="fp32"):
     info = (ctypes.c_double * 8)()
     check(lib().tn_plan_info(d, chi, PRECISIONS[precision], info))
+    gemm = (ctypes.c_double * 2)()
+    check(lib().tn_plan_gemm_flops(d, chi, PRECISIONS[precision], gemm))
     return dict(flops=info[0], scratch_bytes=info[1], lds_bytes=info[2], sites=int(info[3]),
-                rows=int(info[4]), group=int(info[5]), wg_per_cu=int(info[6]), flops_syndrome=info[7])
+                rows=int(info[4]), group=int(info[5]), wg_per_cu=int(info[6]), flops_syndrome=info[7],
+                gemm_flops=gemm[0], gemm_flops_syndrome=gemm[1])
 
 
 def set_tuning(d, chi, precision, group=0, wg_per_cu=0):

@@ -72,6 +72,7 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
   std::vector<uint8_t> init_qi(nsite, 1);
   std::vector<int64_t> region(nsite, 1);
   double flops = 0.0;
+  double gemm = 0.0;  // GEMM-class part
   PlanHeader h{};
   h.d = d;
   h.n = n;
@@ -238,16 +239,25 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
       double m = S.m, nn = (double)S.qo * S.kr;
       double R = (double)S.Dl_new * S.qo, k2 = std::min(R, (double)S.kr);
       flops += 2.0 * S.Dl_old * S.qi * S.Dr_old * S.A * S.qo * S.B;  // MPO apply
-      flops += 2.0 * m * S.qo * rB * S.kr;                              // (W A) . L
+      const double tl = 2.0 * m * S.qo * rB * S.kr;                     // (W A) . L
       flops += qr_flops(m, nn) + orgq_flops(nn, S.k);                  // LQ + explicit Q
-      flops += 2.0 * S.Dl_new * S.k * nn;                               // C . Q
+      const double cq = 2.0 * S.Dl_new * S.k * nn;                      // C . Q
       flops += qr_flops(R, S.kr) + orgq_flops(R, k2);                  // QR of the site matrix + Q
-      if (S.Dr_new < k2)                                                // bond truncated:
-        flops += svd_flops(S.kr, k2) + 2.0 * R * k2 * S.Dr_new;        //   SVD of R factor + A = Q W
+      double qw = 0.0;
+      if (S.Dr_new < k2) {                                              // bond truncated:
+        flops += svd_flops(S.kr, k2);                                   //   SVD of the R factor
+        qw = 2.0 * R * k2 * S.Dr_new;                                   //   A = Q W
+      }
+      flops += tl + cq + qw;
+      gemm += tl + cq + qw;
     }
-    if (u + 1 == h.shared_rows) h.flops_shared = flops;
+    if (u + 1 == h.shared_rows) {
+      h.flops_shared = flops;
+      h.flops_gemm_shared = gemm;
+    }
   }
   h.flops_fwd = flops;
+  h.flops_gemm = gemm;
 
   // --- bottom-up sweep (adjoint): the transposed row MPOs applied from the
   // last row upwards to the all-ones closing state; same bond bookkeeping ---

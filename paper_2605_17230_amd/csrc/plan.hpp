@@ -93,6 +93,8 @@ struct PlanHeader {  // device-visible, followed by the tables at the offsets be
                         // their MPOs, hence the MPS after them, are the same for all four cosets
   double flops_fwd;     // counted flops of one coset's contraction (see count in plan.cpp)
   double flops_shared;  // the part of flops_fwd spent in rows 0..shared_rows-1
+  double flops_gemm;         // GEMM-class part of flops_fwd (T.L, C.Q, and Q.W on truncated bonds)
+  double flops_gemm_shared;  // the part of flops_gemm spent in rows 0..shared_rows-1
 };
 
 struct Plan {

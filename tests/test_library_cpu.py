@@ -72,3 +72,14 @@ def test_plan_info_counts():
     assert a["lds_bytes"] <= 160 * 1024
     with pytest.raises(tn.TNError):
         tn.plan_info(4, 8, "fp32")
+
+
+@pytest.mark.parametrize("d,chi", [(3, 0), (9, 16), (17, 32)])
+def test_gemm_flops_are_part_of_the_counted_work(L, d, chi):
+    """tn_plan_gemm_flops: the GEMM-class part of the counted forward work, per
+    coset and per syndrome as executed (shared rows once, as for the total)."""
+    import paper_2605_17230_amd as tn
+    i = tn.plan_info(d, chi, "bf16")
+    assert 0 < i["gemm_flops"] < i["flops"]
+    assert i["gemm_flops"] <= i["gemm_flops_syndrome"] <= 4 * i["gemm_flops"]
+    assert i["gemm_flops_syndrome"] < i["flops_syndrome"]

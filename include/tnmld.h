@@ -28,10 +28,23 @@
  * default stream); results are valid after the caller synchronises it.
  *
  * Errors: argument validation is synchronous and returns a negative
- * tn_status with nothing enqueued; tn_last_error() then describes it.  No
+ * tn_status with nothing enqueued; tn_last_error() then describes it.  Input
+ * VALUES live in device memory and are checked by the kernels themselves:
+ * a syndrome whose bytes are not all 0/1, whose model index is outside
+ * [0, n_models), or whose noise model has a rate outside [0, 1], a NaN rate or
+ * p_X + p_Y + p_Z > 1 (+1e-12) gets log Z = -INFINITY for all four cosets (and
+ * no gradient contribution); the call records this in the status word of its
+ * workspace, which tn_workspace_status() reads back as TN_EINVAL.  No
  * exception crosses this interface and NaN is never written: an impossible
  * coset has log Z = -INFINITY; an impossible syndrome gives log P = -INFINITY
- * and class 0.
+ * and class 0.  When every Pauli of every qubit has a positive probability,
+ * every coset has Z > 0, so a contraction that comes out with Z <= 0 is a
+ * loss of precision, written as -INFINITY: if all four cosets of a syndrome
+ * are lost, log P(s) is lost and the call records TN_ENUMERIC; if only some
+ * are, those cosets lie below the resolution of the precision form at that
+ * syndrome (improbable cosets whose weight the truncated, rounded boundary
+ * state cannot carry), and the call counts them (tn_workspace_status).  With
+ * some rates zero, -INFINITY may be exact and is not recorded.
  */
 #ifndef TNMLD_H
 #define TNMLD_H
@@ -49,7 +62,7 @@ typedef enum {
   TN_ENOMEM = -2,        /* the library could not allocate its plan cache */
   TN_EDEVICE = -3,       /* no usable HIP device, or a HIP runtime error */
   TN_EUNSUPPORTED = -4,  /* valid request the build cannot run (e.g. chi too large for LDS) */
-  TN_ENUMERIC = -5
+  TN_ENUMERIC = -5       /* precision breakdown seen on the device (reported by tn_workspace_status) */
 } tn_status;
 
 typedef enum {
@@ -162,6 +175,20 @@ int tn_plan_gemm_flops(int32_t d, int32_t chi, int32_t precision, double* out);
  * LDS allows).  group = wg_per_cu = 0 restores the default.  The autotuner
  * sets these from its cache.  Returns TN_OK or TN_EINVAL. */
 int tn_set_tuning(int32_t d, int32_t chi, int32_t precision, int32_t group, int32_t wg_per_cu);
+
+/* Status of the last tn_coset_loglik / tn_decode_batch /
+ * tn_coset_loglik_backward call that used `workspace` (its input-value checks
+ * and numerical health, see "Errors" above).  Synchronises `stream` (the
+ * stream of that call) and reads the status word from the workspace header.
+ * Returns TN_OK, TN_EINVAL (invalid input values were seen; those syndromes
+ * got log Z = -INFINITY), TN_ENUMERIC (all four cosets of some syndrome of a
+ * strictly positive model came out with Z <= 0), or TN_EDEVICE (the stream
+ * failed, e.g. a device fault).  unresolved_cosets (HOST, may be NULL):
+ * receives the number of cosets of strictly positive models written as
+ * -INFINITY while another coset of their syndrome was finite (below the
+ * form's resolution; not an error).  ws_bytes: size of the workspace
+ * (>= 256). */
+int tn_workspace_status(const void* workspace, size_t ws_bytes, void* stream, int64_t* unresolved_cosets);
 
 /* Message for the last non-OK status returned on this thread. */
 const char* tn_last_error(void);

@@ -4,8 +4,9 @@ The contraction runs in ``libtnmld.so`` (HIP, gfx950); this package only
 marshals arguments.  See include/tnmld.h for the C ABI.
 """
 from ._lib import TNError, lib, LIB_PATH  # noqa: F401
-from .api import (SegmentInput, SegmentOutput, code_stabilizers, coset_loglik, coset_loglik_backward,  # noqa: F401
-                  decode, decode_segments, log_posterior, plan_info, set_tuning)
+from .api import (SegmentInput, SegmentOutput, check_input_values, code_stabilizers, coset_loglik,  # noqa: F401
+                  coset_loglik_backward, decode, decode_segments, log_posterior, plan_info, set_tuning,
+                  workspace_bytes)
 from .fit import fit_log_rates  # noqa: F401
 
 from . import tune as _tune  # noqa: E402
@@ -15,5 +16,6 @@ try:  # apply the autotuner's cached launch shapes (needs only the host library)
 except Exception:  # a missing or unreadable cache keeps the defaults
     pass
 
-__all__ = ["TNError", "SegmentInput", "SegmentOutput", "coset_loglik", "coset_loglik_backward", "log_posterior", "decode", "decode_segments",
-           "fit_log_rates", "plan_info", "set_tuning", "code_stabilizers", "lib", "LIB_PATH"]
+__all__ = ["TNError", "SegmentInput", "SegmentOutput", "coset_loglik", "coset_loglik_backward", "log_posterior",
+           "decode", "decode_segments", "check_input_values", "workspace_bytes", "fit_log_rates", "plan_info",
+           "set_tuning", "code_stabilizers", "lib", "LIB_PATH"]

@@ -8,20 +8,48 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import PRECISIONS, Segment, check, lib
+from ._lib import PRECISIONS, Segment, lib
+from ._lib import check as check_rc
 
 _workspaces: dict = {}
+_retired: list = []  # buffers a captured graph may still write: never freed
 
 
-def workspace(nbytes: int, device) -> torch.Tensor:
-    """Per-device scratch buffer, grown on demand and reused across calls."""
+def _stream_ptr(stream, device) -> int:
+    if stream is None:
+        return torch.cuda.current_stream(device).cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _torch_stream(stream, device):
+    if stream is None:
+        return torch.cuda.current_stream(device)
+    if isinstance(stream, torch.cuda.Stream):
+        return stream
+    return torch.cuda.ExternalStream(int(stream), device=device)
+
+
+def workspace(nbytes: int, device, stream=None) -> torch.Tensor:
+    """Scratch buffer of one (device, stream), grown on demand and reused by
+    later calls on that stream (calls on one stream are ordered, so they never
+    overlap in it).  A buffer that was used while the stream was being
+    captured into a graph stays allocated when it is outgrown: the graph keeps
+    its address."""
     dev = torch.device(device)
-    key = (dev.type, dev.index if dev.index is not None else torch.cuda.current_device())
-    buf = _workspaces.get(key)
-    if buf is None or buf.numel() < nbytes:
-        buf = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)
-        _workspaces[key] = buf
-    return buf
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    key = (idx, _stream_ptr(stream, dev))
+    ent = _workspaces.get(key)
+    capturing = torch.cuda.is_current_stream_capturing()
+    if ent is None or ent[0].numel() < nbytes:
+        if ent is not None and ent[1]:
+            _retired.append(ent[0])
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
+        ent = [buf, False]
+        _workspaces[key] = ent
+    ent[1] = ent[1] or capturing
+    return ent[0]
 
 
 def _ptr(t):
@@ -31,6 +59,28 @@ def _ptr(t):
 def _need_cuda(t, name):
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+
+
+def check_input_values(syndromes, rates, model_index=None):
+    """Value checks of one segment's inputs (any device; one host read-back):
+    syndrome bytes in {0, 1}, model indices in [0, M), rates in [0, 1] with no
+    NaN and p_X + p_Y + p_Z <= 1 + 1e-12 per qubit.  Raises ValueError.  The
+    kernels repeat these checks per syndrome (tn_workspace_status)."""
+    r = rates if rates.dim() == 3 else rates.unsqueeze(0)
+    flags = [(syndromes > 1).any()]
+    ok01 = (r >= 0) & (r <= 1)  # False for NaN
+    flags.append(~ok01.all())
+    flags.append((r.sum(-1) > 1.0 + 1e-12).any())
+    if model_index is not None and model_index.numel() > 0:
+        flags.append((model_index < 0).any() | (model_index >= r.shape[0]).any())
+    else:
+        flags.append(torch.zeros((), dtype=torch.bool, device=r.device))
+    bad = torch.stack([f.to(torch.bool).reshape(()) for f in flags]).tolist()
+    what = ["a syndrome byte above 1", "a rate outside [0, 1] or NaN", "p_X + p_Y + p_Z above 1",
+            "a model index outside [0, %d)" % r.shape[0]]
+    msg = [w for w, b in zip(what, bad) if b]
+    if msg:
+        raise ValueError("invalid decoder inputs: " + ", ".join(msg))
 
 
 @dataclass
@@ -51,7 +101,7 @@ class SegmentOutput:
     cls: torch.Tensor    # uint8 [B]
 
 
-def _prepare(segs):
+def _prepare(segs, check=True):
     if not 1 <= len(segs) <= _lib.TN_MAX_SEGMENTS:
         raise ValueError("between 1 and 16 segments per call")
     arr = (Segment * len(segs))()
@@ -72,6 +122,10 @@ def _prepare(segs):
         if s.model_index is not None:
             _need_cuda(s.model_index, "model_index")
             mi = s.model_index.to(torch.int32).contiguous()
+            if mi.shape != (syn.shape[0],):
+                raise ValueError("model_index must be [B]")
+        if check:
+            check_input_values(syn, rates, mi)
         b = syn.shape[0]
         dev = syn.device
         o = SegmentOutput(torch.empty((b, 4), dtype=torch.float64, device=dev),
@@ -81,24 +135,90 @@ def _prepare(segs):
                          mi.data_ptr() if mi is not None else None, syn.data_ptr(), b,
                          o.logz.data_ptr(), o.logp.data_ptr(), o.cls.data_ptr())
         outs.append(o)
-        keep += [syn, rates, mi]
+        keep += [t for t in (syn, rates, mi) if t is not None]
     return arr, outs, keep
 
 
-def decode_segments(segs, tie_tol: float = 1e-9, stream=None):
-    """Decode several segments in one persistent launch per precision."""
-    arr, outs, keep = _prepare(segs)
+def _launch_stream(stream, dev, keep, outs):
+    """Raw stream pointer of the launch; when it is not the current stream,
+    the temporaries and outputs (allocated on the current stream) are marked
+    as used by it, so the caching allocator does not hand their memory out
+    while the kernels may still read or write it."""
+    cur = torch.cuda.current_stream(dev)
+    ptr = _stream_ptr(stream, dev)
+    if ptr != cur.cuda_stream:
+        ts = _torch_stream(stream, dev)
+        for t in keep:
+            t.record_stream(ts)
+        for o in outs:
+            for t in (o.logz, o.logp, o.cls):
+                t.record_stream(ts)
+    return ptr
+
+
+class UnresolvedCosetsWarning(RuntimeWarning):
+    """Some cosets of strictly positive noise models came out with Z <= 0 in
+    a reduced-precision form and were reported as -inf (below the form's
+    resolution at their syndrome; log P(s) and the class are unaffected)."""
+
+
+def _check_status(ws, st_ptr):
+    """Read the call's status word (synchronises the stream): raises TNError
+    for TN_EINVAL (invalid input values) and TN_ENUMERIC (a syndrome's log P(s)
+    was lost); warns with the count of unresolved cosets.  Returns that count."""
+    cnt = ctypes.c_int64(0)
+    check_rc(lib().tn_workspace_status(ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(st_ptr),
+                                       ctypes.byref(cnt)))
+    if cnt.value:
+        import warnings
+        warnings.warn("%d coset(s) below the resolution of the precision form were reported as log Z = -inf"
+                      % cnt.value, UnresolvedCosetsWarning, stacklevel=3)
+    return int(cnt.value)
+
+
+def decode_segments(segs, tie_tol: float = 1e-9, stream=None, workspace_buf=None, check: bool = True):
+    """Decode several segments in one persistent launch per precision.
+
+    stream: torch.cuda.Stream or raw hipStream_t (default: the current
+    stream).  workspace_buf: caller-owned uint8 device tensor of at least
+    workspace_bytes(segs) bytes (default: a buffer kept per device and
+    stream).  check: True validates the input values on the host before the
+    launch and reads the call's status word after it (TN_EINVAL, TN_ENUMERIC;
+    both synchronise), "device" only reads the status word, False neither;
+    both are skipped while the stream is being captured into a graph."""
+    capturing = torch.cuda.is_current_stream_capturing()
+    do_check = bool(check) and not capturing
+    arr, outs, keep = _prepare(segs, do_check and check != "device")
     L = lib()
     nbytes = L.tn_workspace_size(arr, len(segs), 0)
     if nbytes == 0:
-        check(_lib.TN_EINVAL if not L.tn_last_error() else -1)
+        check_rc(_lib.TN_EINVAL if not L.tn_last_error() else -1)
     dev = segs[0].syndromes.device
-    ws = workspace(nbytes, dev)
-    st = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
-    check(L.tn_decode_batch(arr, len(segs), float(tie_tol), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
-                            ctypes.c_void_p(st)))
+    ws = _pick_workspace(workspace_buf, nbytes, dev, stream)
+    st = _launch_stream(stream, dev, keep, outs)
+    check_rc(L.tn_decode_batch(arr, len(segs), float(tie_tol), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                               ctypes.c_void_p(st)))
+    if do_check:
+        _check_status(ws, st)
     del keep
     return outs
+
+
+def _pick_workspace(buf, nbytes, dev, stream):
+    if buf is None:
+        return workspace(nbytes, dev, stream)
+    if buf.dtype != torch.uint8 or not buf.is_cuda or buf.numel() < nbytes:
+        raise ValueError("workspace_buf must be a uint8 device tensor of at least %d bytes" % nbytes)
+    return buf
+
+
+def workspace_bytes(segs, with_backward=False):
+    """Bytes of device workspace a call on these segments needs."""
+    arr, _, _ = _prepare(segs, check=False)
+    n = lib().tn_workspace_size(arr, len(segs), 1 if with_backward else 0)
+    if n == 0:
+        check_rc(_lib.TN_EINVAL)
+    return int(n)
 
 
 def decode(syndromes, rates, d, chi, precision="fp32", model_index=None, tie_tol=1e-9):
@@ -107,27 +227,34 @@ def decode(syndromes, rates, d, chi, precision="fp32", model_index=None, tie_tol
     return o.logz, o.logp, o.cls
 
 
-def coset_loglik(syndromes, rates, d, chi, precision="fp32", model_index=None):
+def coset_loglik(syndromes, rates, d, chi, precision="fp32", model_index=None, check=True):
     """log Z_l(s) [B,4] and log P(s) [B]."""
-    arr, outs, keep = _prepare([SegmentInput(d, chi, syndromes, rates, model_index, precision)])
+    do_check = check and not torch.cuda.is_current_stream_capturing()
+    arr, outs, keep = _prepare([SegmentInput(d, chi, syndromes, rates, model_index, precision)], do_check)
     L = lib()
     nbytes = L.tn_workspace_size(arr, 1, 0)
+    if nbytes == 0:
+        check_rc(_lib.TN_EINVAL)
     ws = workspace(nbytes, syndromes.device)
     st = torch.cuda.current_stream(syndromes.device).cuda_stream
-    check(L.tn_coset_loglik(arr, 1, ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(st)))
+    check_rc(L.tn_coset_loglik(arr, 1, ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(st)))
+    if do_check:
+        _check_status(ws, st)
     del keep
     return outs[0].logz, outs[0].logp
 
 
-def coset_loglik_backward(segs, grad_logp, stream=None, outputs=None):
+def coset_loglik_backward(segs, grad_logp, stream=None, outputs=None, workspace_buf=None, check=True):
     """d (sum_b grad_logp[b] log P(s_b)) / d ln rates for each segment.
 
     grad_logp: list of float64 [B] device tensors, one per segment.  outputs:
     the SegmentOutput list of an earlier decode of exactly these inputs, whose
     log Z / log P(s) are then reused instead of recomputed.  Returns
     (outputs, grads) with grads[i] float64 [M, d*d, 3] (a fresh zeroed tensor
-    that the library accumulates into)."""
-    arr, outs, keep = _prepare(segs)
+    that the library accumulates into).  stream, workspace_buf, check: as for
+    decode_segments."""
+    do_check = bool(check) and not torch.cuda.is_current_stream_capturing()
+    arr, outs, keep = _prepare(segs, do_check and check != "device")
     forward_done = 0
     if outputs is not None:
         if len(outputs) != len(segs):
@@ -143,9 +270,9 @@ def coset_loglik_backward(segs, grad_logp, stream=None, outputs=None):
     L = lib()
     nbytes = L.tn_workspace_size(arr, len(segs), 1)
     if nbytes == 0:
-        check(_lib.TN_EINVAL if not L.tn_last_error() else -1)
+        check_rc(_lib.TN_EINVAL if not L.tn_last_error() else -1)
     dev = segs[0].syndromes.device
-    ws = workspace(nbytes, dev)
+    ws = _pick_workspace(workspace_buf, nbytes, dev, stream)
     gp = [g.to(device=dev, dtype=torch.float64).contiguous() for g in grad_logp]
     grads = []
     for s, g in zip(segs, gp):
@@ -155,9 +282,11 @@ def coset_loglik_backward(segs, grad_logp, stream=None, outputs=None):
         grads.append(torch.zeros((m, s.d * s.d, 3), dtype=torch.float64, device=dev))
     gp_arr = (ctypes.c_void_p * len(segs))(*[g.data_ptr() for g in gp])
     gr_arr = (ctypes.c_void_p * len(segs))(*[g.data_ptr() for g in grads])
-    st = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
-    check(L.tn_coset_loglik_backward(arr, len(segs), gp_arr, gr_arr, forward_done, ctypes.c_void_p(ws.data_ptr()),
-                                     ws.numel(), ctypes.c_void_p(st)))
+    st = _launch_stream(stream, dev, keep + gp + grads, outs)
+    check_rc(L.tn_coset_loglik_backward(arr, len(segs), gp_arr, gr_arr, forward_done, ctypes.c_void_p(ws.data_ptr()),
+                                        ws.numel(), ctypes.c_void_p(st)))
+    if do_check:
+        _check_status(ws, st)
     del keep
     return outs, grads
 
@@ -194,9 +323,9 @@ def log_posterior(log_rates, syndromes, d, chi, precision="fp32", model_index=No
 
 def plan_info(d, chi, precision="fp32"):
     info = (ctypes.c_double * 8)()
-    check(lib().tn_plan_info(d, chi, PRECISIONS[precision], info))
+    check_rc(lib().tn_plan_info(d, chi, PRECISIONS[precision], info))
     gemm = (ctypes.c_double * 2)()
-    check(lib().tn_plan_gemm_flops(d, chi, PRECISIONS[precision], gemm))
+    check_rc(lib().tn_plan_gemm_flops(d, chi, PRECISIONS[precision], gemm))
     return dict(flops=info[0], scratch_bytes=info[1], lds_bytes=info[2], sites=int(info[3]),
                 rows=int(info[4]), group=int(info[5]), wg_per_cu=int(info[6]), flops_syndrome=info[7],
                 gemm_flops=gemm[0], gemm_flops_syndrome=gemm[1])
@@ -204,7 +333,7 @@ def plan_info(d, chi, precision="fp32"):
 
 def set_tuning(d, chi, precision, group=0, wg_per_cu=0):
     """Launch shape for (d, chi, precision); zeros restore the default."""
-    check(lib().tn_set_tuning(d, chi, PRECISIONS[precision], group, wg_per_cu))
+    check_rc(lib().tn_set_tuning(d, chi, PRECISIONS[precision], group, wg_per_cu))
 
 
 def code_stabilizers(d):
@@ -214,5 +343,5 @@ def code_stabilizers(d):
     s = np.zeros((m, 4), np.int32)
     rc = lib().tn_code_stabilizers(d, t.ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p))
     if rc < 0:
-        check(rc)
+        check_rc(rc)
     return t, s

@@ -20,8 +20,10 @@ namespace tnmld {
 // weights of every qubit on it.  top: compact Psi_{u-1} (dims of the forward
 // row's input), bot: Phi_u in site regions (dims of the bottom-up row's
 // input).  Accumulates weight * d log Z / d theta into part[q*3 + k].
+// Returns false when the sandwich value <Phi_u| T_u |Psi_{u-1}> vanished
+// (nothing is added).
 template <typename Real>
-__device__ void row_gradient(const SiteStep* frow, const SiteStep* brow, int nsite, const uint8_t* codes,
+__device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsite, const uint8_t* codes,
                              const double* rates, const uint8_t* fbits, const Real* top, const Real* bot,
                              const int64_t* region, Real* env, Real* P1, Real* P2, Real* P3, Real* Wv,
                              double weight, double* part) {
@@ -102,7 +104,7 @@ __device__ void row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
     __syncthreads();
   }
   const double S = (double)env[s_eoff[nsite]];
-  if (!(fabs(S) > 0.0)) return;  // uniform: every thread read the same value
+  if (!(fabs(S) > 0.0)) return false;  // uniform: every thread read the same value
   // --- right environments and the derivative tensor of each site -----------
   if (tid == 0) env[s_roff[nsite]] = Real(1);
   __syncthreads();
@@ -183,6 +185,7 @@ __device__ void row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
     });
     __syncthreads();
   }
+  return true;
 }
 
 // Backward of syndrome b over its four cosets: adds, for each coset mlog,
@@ -213,7 +216,9 @@ __device__ void adjoint_syndrome(const JobDev& job, int64_t b, uint8_t* smem, co
   __shared__ int s_label;
   __shared__ double s_weight[4];
   Work<Real, Fac> w = carve<Real, Fac>(smem, lay, s_flags);
-  const int model = job.model_index ? job.model_index[b] : 0;
+  const ItemCheck ck = check_item(job, b, n, m);
+  if (!ck.valid) return;  // no contribution; the status word says why
+  const int model = ck.model;
   const double* rates = job.rates + (int64_t)model * n * 3;
   const uint8_t* syn = job.syn + b * m;
   int first = -1;
@@ -308,8 +313,10 @@ __device__ void adjoint_syndrome(const JobDev& job, int64_t b, uint8_t* smem, co
       if (!alive) break;
       const SiteStep* frow = steps + (int64_t)u * nsite;
       const SiteStep* brow = bsteps + (int64_t)(nstep - 1 - u) * nsite;
-      row_gradient<Real>(frow, brow, nsite, codes, rates, w.fbits, sbase + (int64_t)(u - c * kseg) * me, bot, region,
-                         env, P1, P2, P3, w.Wv, weight, pm);
+      if (!row_gradient<Real>(frow, brow, nsite, codes, rates, w.fbits, sbase + (int64_t)(u - c * kseg) * me, bot,
+                              region, env, P1, P2, P3, w.Wv, weight, pm) &&
+          ck.positive && threadIdx.x == 0 && job.status)
+        atomicOr(job.status, ST_NUMERIC);
       if (u > 0) alive = row_step_outlined<Real, Fac, GM>(brow, nsite, codes, rates, bot, region, w, bscale);
     }
   }

@@ -27,6 +27,7 @@ struct JobDev {
   int64_t part_ofs;     // backward: offset of this segment in a work-group's partial gradient
   int32_t n_models;
   int32_t pad;
+  unsigned* status;     // status word of the call (ST_* bits), in the workspace header
 };
 
 struct JobTable {
@@ -40,13 +41,75 @@ __device__ inline int pauli_code(int x, int z) { return x ? (z ? 2 : 1) : (z ? 3
 __device__ inline int pauli_x(int p) { return p == 1 || p == 2; }
 __device__ inline int pauli_z(int p) { return p == 2 || p == 3; }
 
-// p_q(f_q xor P) for the four P, from FP64 rates
+// p_q(f_q xor P) for the four P, from FP64 rates; p_I = 1 - p_X - p_Y - p_Z,
+// never below zero (sums a rounding step above one are accepted as inputs)
 template <typename Real>
 __device__ inline Real pauli_weight(const double* rq, int fb, int P) {
   const int x = pauli_x(P) ^ (fb & 1), z = pauli_z(P) ^ (fb >> 1);
   const int e = pauli_code(x, z);
-  if (e == 0) return Real(1.0 - rq[0] - rq[1] - rq[2]);
+  if (e == 0) return Real(fmax(1.0 - rq[0] - rq[1] - rq[2], 0.0));
   return Real(rq[e - 1]);
+}
+
+// Bits a call ORs into the status word of its workspace.  The status word is
+// followed (8 bytes on) by a 64-bit count of unresolved cosets.
+enum : unsigned {
+  ST_BAD_INPUT = 1u,   // an item had a syndrome byte above 1, a model index out of range, or invalid rates
+  ST_NUMERIC = 2u,     // all four cosets of a strictly positive model came out with Z <= 0: log P(s) was lost
+  ST_UNRESOLVED = 4u   // some (not all) cosets of a strictly positive model came out with Z <= 0: they lie
+                       // below the resolution of the form at that syndrome and are reported as -inf
+};
+// Slack on p_X + p_Y + p_Z <= 1 for rates that were rounded from a sum of one
+constexpr double kRateSlack = 1e-12;
+
+struct ItemCheck {
+  int model;      // model index to read (0 when the item is invalid)
+  bool valid;     // the item may be contracted
+  bool positive;  // every Pauli of every qubit has probability > 0: every coset then has Z > 0
+};
+
+// Input check of syndrome b (collective): syndrome bytes in {0, 1}, model
+// index in [0, n_models), and the model's rates in [0, 1] (NaN fails) with
+// p_X + p_Y + p_Z <= 1.  An invalid item raises ST_BAD_INPUT.
+__device__ inline ItemCheck check_item(const JobDev& job, int64_t b, int n, int m) {
+  const int tid = threadIdx.x;
+  const int raw = job.model_index ? job.model_index[b] : 0;
+  const bool mok = raw >= 0 && raw < job.n_models;
+  const int model = mok ? raw : 0;
+  const uint8_t* sy = job.syn + b * m;
+  int bad = mok ? 0 : 1;
+  for (int j = tid; j < m; j += NT) bad |= sy[j] > 1 ? 1 : 0;
+  const double* r = job.rates + (int64_t)model * n * 3;
+  int pos = 1;
+  for (int q = tid; q < n; q += NT) {
+    const double a = r[3 * q], bb = r[3 * q + 1], c = r[3 * q + 2];
+    const bool in01 = a >= 0.0 && a <= 1.0 && bb >= 0.0 && bb <= 1.0 && c >= 0.0 && c <= 1.0;
+    const double s = a + bb + c;
+    if (!in01 || !(s <= 1.0 + kRateSlack)) bad = 1;
+    if (!(a > 0.0 && bb > 0.0 && c > 0.0 && s < 1.0)) pos = 0;
+  }
+  bad = __syncthreads_or(bad);
+  pos = __syncthreads_and(pos);
+  if (bad && tid == 0 && job.status) atomicOr(job.status, ST_BAD_INPUT);
+  return ItemCheck{model, bad == 0, bad == 0 && pos != 0};
+}
+
+// log Z of a finished coset, never NaN: a result that is not finite (the
+// state vanished or the closing sum was <= 0) is written as -inf.
+__device__ inline double finish_logz(double lz) { return (lz > -INFINITY && lz < INFINITY) ? lz : -INFINITY; }
+
+// After the four cosets of an item (one thread): dead = cosets written as
+// -inf.  Under a strictly positive model every coset has Z > 0, so these are
+// precision losses: all four lose log P(s) (ST_NUMERIC); fewer are cosets
+// below the resolution of the form (ST_UNRESOLVED, counted).
+__device__ inline void report_dead(int dead, const ItemCheck& ck, const JobDev& job) {
+  if (!ck.positive || dead == 0 || !job.status) return;
+  if (dead >= 4) {
+    atomicOr(job.status, ST_NUMERIC);
+  } else {
+    atomicOr(job.status, ST_UNRESOLVED);
+    atomicAdd(reinterpret_cast<unsigned long long*>(job.status + 2), (unsigned long long)dead);
+  }
 }
 
 // Forward contraction of one item; returns log Z (FP64).  Writes the class
@@ -463,8 +526,13 @@ __device__ void contract_syndrome(const JobDev& job, int64_t b, uint8_t* smem, c
   __shared__ int s_flags[2];
   __shared__ int s_label;
   Work<Real, Fac> w = carve<Real, Fac>(smem, lay, s_flags);
-  const int model = job.model_index ? job.model_index[b] : 0;
-  const double* rates = job.rates + (int64_t)model * n * 3;
+  const ItemCheck ck = check_item(job, b, n, m);
+  if (!ck.valid) {  // defined outputs (Z = 0 for every coset) and the status bit
+    if (threadIdx.x < 4) job.logz[b * 4 + threadIdx.x] = -INFINITY;
+    __syncthreads();
+    return;
+  }
+  const double* rates = job.rates + (int64_t)ck.model * n * 3;
   const SiteStep* rowS = steps + (int64_t)ushare * nsite;
   auto dims = [rowS](int J, int& Dl, int& q, int& Dr) {
     Dl = rowS[J].Dl_old;
@@ -484,9 +552,11 @@ __device__ void contract_syndrome(const JobDev& job, int64_t b, uint8_t* smem, c
       if (threadIdx.x == 0) job.logz[b * 4 + label] = -INFINITY;
       __syncthreads();
     }
+    if (threadIdx.x == 0) report_dead(4, ck, job);
     return;
   }
   if (ushare < nstep) mps_pack(scr, region, nsite, dims, snap, false, scr);
+  int dead = 0;  // thread 0: cosets written as -inf
   for (int mlog = 0; mlog < 4; ++mlog) {
     if (mlog > 0) mps_pack(scr, region, nsite, dims, snap, true, scr);
     const int label = prep_reference(H, checks, job.syn + b * m, mlog, w.syn, w.fbits, &s_label);
@@ -494,10 +564,14 @@ __device__ void contract_syndrome(const JobDev& job, int64_t b, uint8_t* smem, c
     bool ok = true;
     for (int u = ushare; u < nstep && ok; ++u)
       ok = row_step<Real, Fac, GM>(steps + (int64_t)u * nsite, nsite, codes, rates, scr, region, w, logscale);
-    const double lz = ok ? logscale + mps_close<Real, Fac>(scr, region, fin, nsite, w.sig) : -INFINITY;
-    if (threadIdx.x == 0) job.logz[b * 4 + label] = lz;
+    const double lz = finish_logz(ok ? logscale + mps_close<Real, Fac>(scr, region, fin, nsite, w.sig) : -INFINITY);
+    if (threadIdx.x == 0) {
+      job.logz[b * 4 + label] = lz;
+      dead += lz == -INFINITY;
+    }
     __syncthreads();
   }
+  if (threadIdx.x == 0) report_dead(dead, ck, job);
 }
 
 

@@ -106,6 +106,13 @@ __global__ void zero_counter(unsigned long long* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0ull;
 }
 
+__global__ void zero_status(unsigned* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st[0] = 0u;
+    *reinterpret_cast<unsigned long long*>(st + 2) = 0ull;
+  }
+}
+
 // log P(s) = logsumexp over the four cosets and the tie-tolerant argmax
 __global__ void decide_kernel(const double* logz, int64_t count, double tie_tol, double* logp, uint8_t* cls) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -354,6 +361,15 @@ struct Launch {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Workspace header (the first kAlign bytes): one work counter per launch, then
+// the status word of the last call (ST_* bits, read by tn_workspace_status)
+// and, 8 bytes on, its 64-bit count of unresolved cosets.
+constexpr size_t kStatusOfs = 128;
+static_assert(sizeof(unsigned long long) * kMaxLaunches <= kStatusOfs, "header layout");
+unsigned* status_word(void* workspace) {
+  return reinterpret_cast<unsigned*>(reinterpret_cast<char*>(workspace) + kStatusOfs);
+}
+
 // Build the launch groups (one per precision) and the workspace layout.
 int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vector<Launch>* out, size_t* ws_bytes,
                   int* nwg, bool allow_small = true) {
@@ -454,8 +470,11 @@ int run_forward(const tn_segment* segs, int32_t nseg, void* workspace, size_t ws
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* base = reinterpret_cast<char*>(workspace);
   size_t off = align_up(sizeof(unsigned long long) * kMaxLaunches);
+  unsigned* status = status_word(workspace);
+  zero_status<<<1, 64, 0, st>>>(status);
   int li = 0;
   for (auto& L : launches) {
+    for (int i = 0; i < L.jt.n; ++i) L.jt.j[i].status = status;
     unsigned long long* counter = reinterpret_cast<unsigned long long*>(base) + li;
     char* scr = base + off;
     off += (size_t)L.nwg * align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
@@ -644,9 +663,14 @@ int tn_coset_loglik_backward(const tn_segment* segs, int32_t nseg, const double*
   char* base = reinterpret_cast<char*>(workspace) + bl.fwd_bytes;
   double* partials = reinterpret_cast<double*>(base);
   char* scratch = base + align_up((size_t)bl.nwg * bl.part_stride * sizeof(double));
+  unsigned* status = status_word(workspace);
+  if (forward_done) zero_status<<<1, 64, 0, st>>>(status);  // else the forward call cleared it
   fill_zero_f64<<<256, 256, 0, st>>>(partials, (int64_t)bl.nwg * bl.part_stride);
   JobTable jt = bl.jt;
-  for (int i = 0; i < jt.n; ++i) jt.j[i].gradp = grad_logp[bl.seg_of_job[i]];
+  for (int i = 0; i < jt.n; ++i) {
+    jt.j[i].gradp = grad_logp[bl.seg_of_job[i]];
+    jt.j[i].status = status;
+  }
   LdsLayout lay = lds_layout(bl.merged, real_bytes(bl.precision), fac_bytes(bl.precision));
   const void* kern = nullptr;
   if (bl.precision == TN_FP64) kern = reinterpret_cast<const void*>(bwd_kernel<double, double, GEMM_VALU>);
@@ -732,6 +756,25 @@ int tn_set_tuning(int32_t d, int32_t chi, int32_t precision, int32_t group, int3
   std::lock_guard<std::mutex> lk(g_mu);
   if (group == 0 && wg_per_cu == 0) g_tune.erase(std::make_tuple(d, chi, precision));
   else g_tune[std::make_tuple(d, chi, precision)] = Tune{group, wg_per_cu};
+  return TN_OK;
+}
+
+int tn_workspace_status(const void* workspace, size_t ws_bytes, void* stream, int64_t* unresolved_cosets) {
+  if (!workspace || ws_bytes < kAlign) return fail(TN_EINVAL, "workspace too small for a status word");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (hipStreamSynchronize(st) != hipSuccess) return fail(TN_EDEVICE, "stream synchronisation failed");
+  unsigned v[4] = {0u, 0u, 0u, 0u};
+  if (hipMemcpy(v, status_word(const_cast<void*>(workspace)), sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(TN_EDEVICE, "status read failed");
+  unsigned long long cnt = 0;
+  std::memcpy(&cnt, v + 2, sizeof(cnt));
+  if (unresolved_cosets) *unresolved_cosets = (v[0] & ST_UNRESOLVED) ? (int64_t)cnt : 0;
+  if (v[0] & ST_BAD_INPUT)
+    return fail(TN_EINVAL, "invalid input values: a syndrome byte above 1, a model index out of range, or rates "
+                           "outside [0, 1] / NaN / p_X + p_Y + p_Z > 1 (those syndromes were given log Z = -inf)");
+  if (v[0] & ST_NUMERIC)
+    return fail(TN_ENUMERIC, "precision breakdown: all four cosets of a syndrome of a strictly positive noise "
+                             "model contracted to Z <= 0 (reported as log Z = -inf)");
   return TN_OK;
 }
 

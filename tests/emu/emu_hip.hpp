@@ -5,6 +5,7 @@
 // of the lanes involved.  Test infrastructure only.
 #pragma once
 #define TNMLD_EMU 1
+#include <atomic>
 #include <barrier>
 #include <cmath>
 #include <cstdint>
@@ -29,6 +30,29 @@ template <class T>
 inline T g_xchg[1024];
 
 inline void __syncthreads() { g_block_bar->arrive_and_wait(); }
+
+// __syncthreads_or / __syncthreads_and: a barrier that also combines one int
+// per thread
+inline std::atomic<int> g_sync_acc{0};
+template <class Op>
+int emu_sync_combine(int v, int init, Op op) {
+  g_block_bar->arrive_and_wait();
+  if (threadIdx.x == 0) g_sync_acc.store(init);
+  g_block_bar->arrive_and_wait();
+  int cur = g_sync_acc.load();
+  while (!g_sync_acc.compare_exchange_weak(cur, op(cur, v))) {
+  }
+  g_block_bar->arrive_and_wait();
+  const int r = g_sync_acc.load();
+  g_block_bar->arrive_and_wait();
+  return r;
+}
+inline int __syncthreads_or(int v) { return emu_sync_combine(v ? 1 : 0, 0, [](int a, int b) { return a | b; }); }
+inline int __syncthreads_and(int v) { return emu_sync_combine(v ? 1 : 0, 1, [](int a, int b) { return a & b; }); }
+inline unsigned atomicOr(unsigned* p, unsigned v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
+inline unsigned long long atomicAdd(unsigned long long* p, unsigned long long v) {
+  return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
+}
 
 // lane t reads the value of lane t ^ off; all lanes of the wave take part
 template <class T>

@@ -39,13 +39,14 @@ void run_block(F f) {
 }
 
 template <typename Real, typename Fac>
-int forward(int d, int chi, int group, const double* rates, const uint8_t* syn, int count, double* logz) {
+int forward(int d, int chi, int group, const double* rates, int n_models, const int32_t* model_index,
+            const uint8_t* syn, int count, double* logz, unsigned* status) {
   Plan p;
   if (!build_plan(d, chi, group, &p).empty()) return -1;
   const LdsLayout lay = lds_layout(p.h, sizeof(Real), sizeof(Fac));
   std::vector<double> smem(lay.bytes / 8 + 16), scr(p.h.scratch_elems * sizeof(Real) / 8 + 16),
       snap(p.h.mps_elems * sizeof(Real) / 8 + 16);
-  JobDev job{p.blob.data(), rates, nullptr, syn, logz, nullptr, nullptr, count, 0, 0, 1, 0};
+  JobDev job{p.blob.data(), rates, model_index, syn, logz, nullptr, nullptr, count, 0, 0, n_models, 0, status};
   Barriers bars;
   for (int b = 0; b < count; ++b)
     run_block([&](int) {
@@ -66,7 +67,7 @@ int gradient(int d, int chi, int group, const double* rates, const uint8_t* syn,
   const int64_t elems = 2 * H.scratch_elems + (int64_t)(ncp + kseg + 1 + H.shared_rows / kseg * kseg) * H.mps_elems +
                        H.env_elems + 3 * H.tmp_elems;
   std::vector<double> smem(lay.bytes / 8 + 16), scr(elems * sizeof(Real) / 8 + 16);
-  JobDev job{p.blob.data(), rates, nullptr, syn, const_cast<double*>(logz), logp, gradp, count, 0, 0, 1, 0};
+  JobDev job{p.blob.data(), rates, nullptr, syn, const_cast<double*>(logz), logp, gradp, count, 0, 0, 1, 0, nullptr};
   Barriers bars;
   for (int b = 0; b < count; ++b)
     run_block([&](int) {
@@ -80,9 +81,20 @@ int gradient(int d, int chi, int group, const double* rates, const uint8_t* syn,
 // precision: 0 = FP64, 1 = FP32 state with FP64 factorisations, 3 = plain FP32
 extern "C" int emu_forward(int d, int chi, int precision, int group, const double* rates, const uint8_t* syn,
                            int count, double* logz) {
-  if (precision == 0) return forward<double, double>(d, chi, group, rates, syn, count, logz);
-  if (precision == 1) return forward<float, double>(d, chi, group, rates, syn, count, logz);
-  return forward<float, float>(d, chi, group, rates, syn, count, logz);
+  if (precision == 0) return forward<double, double>(d, chi, group, rates, 1, nullptr, syn, count, logz, nullptr);
+  if (precision == 1) return forward<float, double>(d, chi, group, rates, 1, nullptr, syn, count, logz, nullptr);
+  return forward<float, float>(d, chi, group, rates, 1, nullptr, syn, count, logz, nullptr);
+}
+
+// the same with noise models selected per syndrome and the call's status word
+extern "C" int emu_forward_models(int d, int chi, int precision, int group, const double* rates, int n_models,
+                                  const int32_t* model_index, const uint8_t* syn, int count, double* logz,
+                                  unsigned* status) {
+  if (precision == 0)
+    return forward<double, double>(d, chi, group, rates, n_models, model_index, syn, count, logz, status);
+  if (precision == 1)
+    return forward<float, double>(d, chi, group, rates, n_models, model_index, syn, count, logz, status);
+  return forward<float, float>(d, chi, group, rates, n_models, model_index, syn, count, logz, status);
 }
 
 extern "C" int emu_gradient(int d, int chi, int precision, int group, const double* rates, const uint8_t* syn,

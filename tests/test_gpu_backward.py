@@ -74,6 +74,13 @@ def rel_err(got, ref):
     return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
 
 
+def elem_err(got, ref, floor):
+    """Largest per-element excess |got - ref| / (|ref| + floor / rtol-free):
+    returns max_i |got_i - ref_i| / (|ref_i| + floor), so a bar r means
+    |got_i - ref_i| <= r |ref_i| + r floor for every element."""
+    return float(np.max(np.abs(got - ref) / (np.abs(ref) + floor)))
+
+
 @pytest.mark.parametrize("d,chi", [(3, 0), (3, 4), (5, 0)])
 def test_grad_exact_fp64(d, chi):
     rates = synth.inhomogeneous(d, 0.01, 0.15, seed=11 + d)
@@ -133,9 +140,11 @@ def test_grad_d11_chi24_central_differences():
     sel = np.array([got[q, k] for q, k in coords])
     fd_gpu = gpu_fd(d, chi, smp["syndromes"], rates, "fp64", gw, coords)
     fd_orc = oracle_fd(d, rates, smp["syndromes"], gw, coords)
-    scale = np.max(np.abs(got))
-    assert np.max(np.abs(sel - fd_gpu)) < 1e-4 * scale
-    assert np.max(np.abs(sel - fd_orc)) < 1e-4 * scale
+    # per element: |g_i - fd_i| <= 1e-4 |fd_i| + 1e-4 * 1e-4 max|g| (the floor
+    # covers the rounding of the differences of sums of log P)
+    floor = 1e-4 * np.max(np.abs(got))
+    assert elem_err(sel, fd_gpu, floor) < 1e-4
+    assert elem_err(sel, fd_orc, floor) < 1e-4
 
 
 def test_grad_full_size_d17_chi32_central_differences():
@@ -149,7 +158,7 @@ def test_grad_full_size_d17_chi32_central_differences():
     coords = [(0, 0), (144, 1), (288, 2), (100, 2)]
     sel = np.array([got[q, k] for q, k in coords])
     fd = gpu_fd(d, chi, smp["syndromes"], rates, "fp64", gw, coords)
-    assert np.max(np.abs(sel - fd)) < 1e-4 * np.max(np.abs(got))
+    assert elem_err(sel, fd, 1e-4 * np.max(np.abs(got))) < 1e-4
 
 
 def test_grad_deterministic_and_zero_weights():
@@ -197,12 +206,24 @@ def test_score_identity():
     assert np.all(np.abs(mean) < 5 * sd / np.sqrt(nb) + 1e-9)
 
 
+# Absolute floor of the per-element gradient bars on the gradient workload
+# (8,192 syndromes): each syndrome adds a term of order 1e-2..1 to a
+# component; FP32 rounding of ~1e-6 relative per term, summed over the batch
+# with random signs, leaves ~1e-4 absolute, about 5e-6 of the largest
+# component (~40).
+C5_FLOOR = 2e-4
+
+
 @pytest.mark.slow
 def test_c5_gradient_full_batch():
-    """The gradient workload (d = 11, per-qubit log-uniform rates, chi = 24):
-    the FP32 adjoint over all 8,192 syndromes against the FP64 adjoint, and the
-    FP64 adjoint against FP64 central differences (step 1e-4 in ln p) on 32
-    random parameters over a 512-syndrome share."""
+    """The gradient workload (d = 11, per-qubit log-uniform rates, chi = 24,
+    all 8,192 syndromes).  Per element, with the stated floor:
+      * the FP32 adjoint against central differences (step 1e-4 in ln p) of the
+        FP64 forward pass over the whole batch, on 32 random parameters:
+        |g_i - fd_i| <= 1e-4 |fd_i| + 1e-4 C5_FLOOR;
+      * the FP32 adjoint against the FP64 adjoint on all 363 parameters:
+        |g32_i - g64_i| <= 1e-4 |g64_i| + C5_FLOOR;
+      * the FP64 adjoint against the same differences at 1e-5."""
     s = synth.config_inputs("C5")[0]
     d, chi = s["d"], s["chi"]
     syn = s["syndromes"]
@@ -210,14 +231,19 @@ def test_c5_gradient_full_batch():
     n = len(syn)
     g32, _, _ = gpu_grad(d, chi, syn, rates, "fp32", np.ones(n))
     g64, _, _ = gpu_grad(d, chi, syn, rates, "fp64", np.ones(n))
-    assert rel_err(g32, g64) < 1e-3
-    sub = syn[:512]
-    gs, _, _ = gpu_grad(d, chi, sub, rates, "fp64", np.ones(512))
+    e = np.abs(g32 - g64)
+    print("C5 FP32 vs FP64 adjoint: max |d| %.3g, max |d| / (|g64| + floor) %.3g"
+          % (e.max(), elem_err(g32, g64, C5_FLOOR)), flush=True)
+    assert np.all(e <= 1e-4 * np.abs(g64) + C5_FLOOR)
     rng = np.random.default_rng(5)
     coords = [(int(q), int(k)) for q, k in zip(rng.integers(0, d * d, 32), rng.integers(0, 3, 32))]
-    fd = gpu_fd(d, chi, sub, rates, "fp64", np.ones(512), coords)
-    sel = np.array([gs[q, k] for q, k in coords])
-    assert np.max(np.abs(sel - fd)) < 1e-4 * np.max(np.abs(gs))
+    fd = gpu_fd(d, chi, syn, rates, "fp64", np.ones(n), coords)
+    a32 = np.array([g32[q, k] for q, k in coords])
+    a64 = np.array([g64[q, k] for q, k in coords])
+    print("C5 vs central differences, 32 parameters: FP32 %.3g, FP64 %.3g (relative, per element)"
+          % (float(np.max(np.abs(a32 - fd) / np.abs(fd))), float(np.max(np.abs(a64 - fd) / np.abs(fd)))), flush=True)
+    assert np.all(np.abs(a32 - fd) <= 1e-4 * np.abs(fd) + 1e-4 * C5_FLOOR)
+    assert np.all(np.abs(a64 - fd) <= 1e-5 * np.abs(fd) + 1e-4 * C5_FLOOR)
 
 
 def test_backward_reuses_forward_outputs():

@@ -1,6 +1,8 @@
 """Mixed batches in one persistent launch (distances 5..15, three Z-biases per
 distance, chi by distance) and replay of a captured launch, against the FP64
 oracle and against single-segment launches."""
+import warnings
+
 import numpy as np
 import pytest
 
@@ -34,47 +36,77 @@ def _oracle_logz(s, idx):
     return out
 
 
-def _check_vs_oracle(s, o, idx):
+# Bars against the exact oracle at the C4 bond dimensions (truncation plus
+# precision error), per form: |delta log P(s)|, and |delta log Z| of every
+# coset whose oracle posterior is >= e^-10.  A reduced-precision form may
+# report a coset far below its syndrome's probable ones as -inf (below the
+# form's resolution, counted by the library); that is accepted only for
+# oracle posteriors below e^-30.
+C4_BARS = {"fp32": dict(logp=1e-4, logz=5e-4), "bf16": dict(logp=2e-3, logz=2e-2)}
+UNRESOLVED_POST = -30.0
+
+
+def _check_vs_oracle(s, o, idx, prec="fp32"):
     ref = _oracle_logz(s, idx)
     lz = o.logz.cpu().numpy()[idx]
     cls = o.cls.cpu().numpy()[idx]
     lp_ref, cls_ref = oracle.decide(ref)
     lp = o.logp.cpu().numpy()[idx]
-    # truncation error at these chi: log P(s) to 1e-2, classes equal unless the
-    # oracle's top-two gap is inside the error
-    assert np.max(np.abs(lp - lp_ref)) < 1e-2, (s["d"], np.max(np.abs(lp - lp_ref)))
+    bar = C4_BARS[prec]
+    dlp = float(np.max(np.abs(lp - lp_ref)))
+    assert dlp < bar["logp"], (s["d"], dlp)
+    fin, gfin = np.isfinite(ref), np.isfinite(lz)
+    assert not (gfin & ~fin).any(), "finite where the oracle says impossible"
+    with np.errstate(invalid="ignore"):
+        post = np.where(fin, ref - lp_ref[:, None], -np.inf)
+    unres = fin & ~gfin
+    assert post[unres].max(initial=-np.inf) < UNRESOLVED_POST, (s["d"], post[unres].max())
+    both = fin & gfin
+    err = np.where(both, np.abs(np.where(both, lz, 0) - np.where(both, ref, 0)), 0.0)
+    dz = float(err[post >= -10].max(initial=0))
+    assert dz < bar["logz"], (s["d"], dz)
     top2 = np.sort(ref, axis=1)[:, -2:]
     clear = (top2[:, 1] - top2[:, 0]) > 2e-2
     assert np.all(cls[clear] == cls_ref[clear])
-    return float(np.max(np.abs(np.where(np.isfinite(ref), lz - ref, 0.0))))
+    print("C4 %s d=%d: max |dlogP| %.3g, max |dlogZ| (post >= e^-10) %.3g, unresolved %d"
+          % (prec, s["d"], dlp, dz, int(unres.sum())), flush=True)
+    return dz
 
 
-def test_c4_mixed_launch_small():
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_c4_mixed_launch_small(prec):
     """Every C4 segment at 1/256 of its count in one call: each against the
-    exact oracle and bitwise against the segment decoded alone."""
+    exact oracle under the form's bars, and bitwise against the segment
+    decoded alone."""
     tn = _tn()
     segs = synth.config_inputs("C4", scale=1 / 256)
-    outs = tn.decode_segments(_inputs(segs))
-    for s, o in zip(segs, outs):
-        _check_vs_oracle(s, o, list(range(len(s["syndromes"]))))
-        alone = tn.decode_segments(_inputs([s]))[0]
-        assert torch.equal(alone.logz, o.logz)
-        assert torch.equal(alone.cls, o.cls)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", tn.api.UnresolvedCosetsWarning)
+        outs = tn.decode_segments(_inputs(segs, prec))
+        for s, o in zip(segs, outs):
+            _check_vs_oracle(s, o, list(range(len(s["syndromes"]))), prec)
+            alone = tn.decode_segments(_inputs([s], prec))[0]
+            assert torch.equal(alone.logz, o.logz)
+            assert torch.equal(alone.cls, o.cls)
 
 
 @pytest.mark.slow
-def test_c4_full_mixed_launch_sampled():
-    """The whole C4 batch (63,488 syndromes, six distances) in one persistent
-    launch; 12 syndromes of every segment against the exact oracle."""
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_c4_full_mixed_launch_sampled(prec):
+    """The whole C4 batch (63,488 syndromes, six distances) in one call (one
+    persistent launch per size class); 12 syndromes of every segment against
+    the exact oracle under the form's bars."""
     tn = _tn()
     segs = synth.config_inputs("C4")
-    outs = tn.decode_segments(_inputs(segs))
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", tn.api.UnresolvedCosetsWarning)
+        outs = tn.decode_segments(_inputs(segs, prec))
     torch.cuda.synchronize()
     rng = np.random.default_rng(4)
     for s, o in zip(segs, outs):
         n = len(s["syndromes"])
         idx = sorted(rng.choice(n, 12, replace=False).tolist())
-        _check_vs_oracle(s, o, idx)
+        _check_vs_oracle(s, o, idx, prec)
         assert np.all(np.isfinite(o.logp.cpu().numpy()))
 
 

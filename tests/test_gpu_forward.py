@@ -63,24 +63,35 @@ def log_posterior(ref):
         return ref - np.logaddexp.reduce(ref, axis=1, keepdims=True)
 
 
+UNRESOLVED_POST = -30.0  # a reduced-precision form may report a coset below e^-30 posterior as -inf
+
+
 def check_logz(got, ref, prec):
     """Apply the bar of the precision form; returns the max abs error."""
     fa, fb = np.isfinite(got), np.isfinite(ref)
-    assert np.array_equal(fa, fb), "finite pattern differs"
     post = np.where(fb, log_posterior(np.where(fb, ref, -np.inf)), -np.inf)
-    err = np.where(fb, np.abs(np.where(fa, got, 0) - np.where(fb, ref, 0)), 0.0)
+    assert not (fa & ~fb).any(), "finite where the oracle says impossible"
+    unres = fb & ~fa
+    if prec in ("fp64", "fp32"):
+        assert not unres.any(), "finite pattern differs"
+    else:
+        assert post[unres].max(initial=-np.inf) < UNRESOLVED_POST
+    both = fa & fb
+    err = np.where(both, np.abs(np.where(both, got, 0) - np.where(both, ref, 0)), 0.0)
     rel = err / np.maximum(1.0, np.abs(np.where(fb, ref, 1.0)))
     if prec == "fp64":
         assert rel[post >= -20].max(initial=0) < 1e-10, rel[post >= -20].max(initial=0)
         assert rel.max(initial=0) < 1e-6, rel.max(initial=0)
     elif prec == "fp32":
         assert err.max(initial=0) < 1e-4, err.max(initial=0)
-    else:
+    elif prec == "fp32plain":
         assert err[post >= -10].max(initial=0) < 1e-3, err[post >= -10].max(initial=0)
+    else:  # bf16 form (split-bf16 contractions, FP32 factorisations)
+        assert err[post >= -10].max(initial=0) < 5e-3, err[post >= -10].max(initial=0)
     return float(err.max(initial=0))
 
 
-BOUND = {"fp64": 1e-9, "fp32": 1e-4, "fp32plain": 1e-3}
+BOUND = {"fp64": 1e-9, "fp32": 1e-4, "fp32plain": 1e-3, "bf16": 5e-3}
 
 
 def check_classes(got_cls, ref_logz, eps):
@@ -118,7 +129,7 @@ def test_d3_fp64_matches_enumeration(dev, c1, chi):
     assert rel_err(logp, rlp) < 1e-10
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp32plain"])
+@pytest.mark.parametrize("prec", ["fp32", "fp32plain", "bf16"])
 def test_d3_single(dev, c1, prec):
     r, smp, ref = c1
     logz, logp, cls = run(dev, 3, 4, prec, smp["syndromes"], r)
@@ -126,7 +137,7 @@ def test_d3_single(dev, c1, prec):
     check_classes(cls, ref, BOUND[prec])
 
 
-@pytest.mark.parametrize("prec,chi", [("fp64", 16), ("fp64", 0), ("fp32", 16), ("fp32plain", 16)])
+@pytest.mark.parametrize("prec,chi", [("fp64", 16), ("fp64", 0), ("fp32", 16), ("fp32plain", 16), ("bf16", 16)])
 def test_d5_exact_vs_transfer(dev, prec, chi):
     d = 5
     r = synth.inhomogeneous(d, 0.005, 0.12, seed=5)
@@ -236,27 +247,61 @@ def test_c2_sweep_fp32plain_vs_exact(dev):
 
 GOLDEN_C3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_oracle_logz.txt")
 
+# Bars of the benchmark's configuration (d = 17, chi = 32) against the exact
+# oracle on the golden syndromes, per form: |delta log P(s)|, |delta log Z| of
+# the cosets with oracle posterior >= e^-10 and >= e^-20.  They include the
+# truncation error at chi = 32 (the FP64 form shows it alone).  Cosets below
+# e^-30 posterior may be unresolved (-inf) in the reduced-precision forms.
+C3_BARS = {
+    "fp64": dict(logp=1e-4, post10=1e-4, post20=1e-3),
+    "fp32": dict(logp=1e-4, post10=1e-4, post20=1e-3),
+    "fp32plain": dict(logp=2e-3, post10=2e-3, post20=3e-2),
+    "bf16": dict(logp=1e-2, post10=1e-2, post20=0.3),
+}
+
 
 @pytest.mark.slow
-@pytest.mark.parametrize("prec", ["bf16", "fp32plain"])
+@pytest.mark.parametrize("prec", ["bf16", "fp32plain", "fp32", "fp64"])
 def test_c3_full_batch_vs_exact(dev, prec):
     """The benchmark's launch (d = 17, chi = 32, all 16,384 syndromes in one
-    call) against the exact oracle values of its first 1,024 syndromes
+    call) against the exact oracle values of its first 4,096 syndromes
     (tests/golden/c3_oracle_logz.txt, written by make_c3_oracle.py from the
-    oracle alone): classes agree on >= 99.9 %, and wherever the oracle's top-two
-    gap exceeds the stated error bound; log P(s) within 1e-2."""
+    oracle alone): per-coset |delta log Z| by posterior band and |delta log P|
+    under the form's bars, classes equal on >= 99.9 % and wherever the
+    oracle's top-two gap exceeds the error bound."""
+    import warnings
     ref = np.loadtxt(GOLDEN_C3)
     r = synth.depolarizing(17, 0.12)
     smp = synth.sample(17, r, 16384, seed=3000)
-    logz, logp, cls = run(dev, 17, 32, prec, smp["syndromes"], r)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", tn.api.UnresolvedCosetsWarning)
+        logz, logp, cls = run(dev, 17, 32, prec, smp["syndromes"], r)
     n = len(ref)
+    bar = C3_BARS[prec]
     lp_ref, cls_ref = oracle.decide(ref)
+    lz = logz[:n]
     err_lp = float(np.max(np.abs(logp[:n] - lp_ref)))
+    fin, gfin = np.isfinite(ref), np.isfinite(lz)
+    assert not (gfin & ~fin).any()
+    post = np.where(fin, log_posterior(np.where(fin, ref, -np.inf)), -np.inf)
+    unres = fin & ~gfin
+    both = fin & gfin
+    err = np.where(both, np.abs(np.where(both, lz, 0) - np.where(both, ref, 0)), 0.0)
+    e10 = float(err[post >= -10].max(initial=0))
+    e20 = float(err[post >= -20].max(initial=0))
+    eall = float(err.max(initial=0))
     agree = float((cls[:n] == cls_ref).mean())
-    print("C3 %s: max |dlogP| %.3g, class agreement %.5f over %d" % (prec, err_lp, agree, n))
-    assert err_lp < 1e-2
+    print("C3 %s over %d: max |dlogP| %.3g; max |dlogZ| posterior >= e^-10 %.3g, >= e^-20 %.3g, all %.3g; "
+          "unresolved %d (max posterior %.1f); class agreement %.5f"
+          % (prec, n, err_lp, e10, e20, eall, int(unres.sum()), post[unres].max(initial=-np.inf), agree),
+          flush=True)
+    assert err_lp < bar["logp"]
+    assert e10 < bar["post10"] and e20 < bar["post20"]
+    assert post[unres].max(initial=-np.inf) < UNRESOLVED_POST
+    if prec in ("fp64", "fp32"):
+        assert not unres.any()
     assert agree >= 0.999
-    check_classes(cls[:n], ref, 0.05)
+    check_classes(cls[:n], ref, bar["post10"])
     assert np.all(np.isfinite(logp))
 
 

@@ -31,6 +31,7 @@ def emu():
     P = ctypes.c_void_p
     L.emu_forward.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_int, P]
     L.emu_gradient.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_int, P, P, P, P]
+    L.emu_forward_models.argtypes = [ctypes.c_int] * 4 + [P, ctypes.c_int, P, P, ctypes.c_int, P, P]
     return L
 
 
@@ -77,3 +78,72 @@ def test_d3_gradient(emu):
                             logp.ctypes.data, gw.ctypes.data, out.ctypes.data) == 0
     ref = sum(w * oracle.grad_logp(3, rates, s)[0] for s, w in zip(syn, gw))
     assert np.max(np.abs(out - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+def forward_models(L, d, chi, prec, rates, model_index, syn):
+    """Forward with per-syndrome models; returns (log Z, status word)."""
+    rates = np.ascontiguousarray(rates, np.float64)
+    if rates.ndim == 2:
+        rates = rates[None]
+    mi = np.ascontiguousarray(model_index, np.int32)
+    syn = np.ascontiguousarray(syn, np.uint8)
+    out = np.full((len(syn), 4), np.nan)
+    st = np.zeros(4, np.uint32)  # status word, then the 64-bit count of unresolved cosets
+    assert L.emu_forward_models(d, chi, prec, 1, rates.ctypes.data, rates.shape[0], mi.ctypes.data, syn.ctypes.data,
+                                len(syn), out.ctypes.data, st.ctypes.data) == 0
+    return out, int(st[0])
+
+
+ST_BAD_INPUT, ST_NUMERIC, ST_UNRESOLVED = 1, 2, 4
+
+
+def test_device_input_checks(emu):
+    """The kernels' own input check: a syndrome byte above 1, a model index
+    out of range, or a model with a negative, NaN or over-unity rate gives
+    log Z = -inf for that syndrome only (never NaN) and raises the status bit
+    the host reads back as TN_EINVAL; valid syndromes are unaffected."""
+    d = 3
+    good = synth.depolarizing(d, 0.1)
+    neg, nan, over = good.copy(), good.copy(), good.copy()
+    neg[4, 1] = -1e-3
+    nan[7, 2] = np.nan
+    over[2] = [0.5, 0.4, 0.2]
+    rates = np.stack([good, neg, nan, over])
+    syn = synth.sample(d, good, 6, seed=3)["syndromes"]
+    ref = oracle.transfer(d, good, syn)
+    out, st = forward_models(emu, d, 0, 0, rates, np.zeros(6), syn)
+    assert st == 0 and np.max(np.abs(out - ref)[np.isfinite(ref)], initial=0) < 1e-12
+    for k, mi, fix in ((0, 1, None), (1, 2, None), (2, 3, None), (3, 4, None), (4, -1, None), (5, 0, "byte")):
+        s2 = syn.copy()
+        m2 = np.zeros(6, np.int32)
+        m2[k] = mi
+        if fix == "byte":
+            s2[k, 3] = 2
+        out, st = forward_models(emu, d, 0, 0, rates, m2, s2)
+        assert st == ST_BAD_INPUT, (k, mi, st)
+        assert np.isneginf(out[k]).all() and not np.isnan(out).any()
+        keep = np.arange(6) != k
+        assert np.array_equal(out[keep], forward_models(emu, d, 0, 0, rates, np.zeros(6), syn)[0][keep])
+
+
+def test_numeric_status_only_for_positive_models(emu):
+    """A coset whose contraction vanishes is impossible when some rates are
+    zero (log Z = -inf, no status), but a precision loss when every Pauli has
+    a positive probability: with rates so small that FP32 underflows them to
+    zero, a syndrome that needs an error loses all four cosets (ST_NUMERIC)
+    and the trivial syndrome keeps coset I and loses the other three
+    (ST_UNRESOLVED, counted), instead of silently reporting impossible
+    cosets."""
+    d = 3
+    zero = np.zeros((d * d, 3))
+    syn = np.zeros((1, d * d - 1), np.uint8)
+    syn[0, 0] = 1
+    out, st = forward_models(emu, d, 0, 3, zero, np.zeros(1), syn)
+    assert st == 0 and np.isneginf(out).all()
+    tiny = np.full((d * d, 3), 1e-46)  # positive in FP64, zero once rounded to FP32
+    out, st = forward_models(emu, d, 0, 3, tiny, np.zeros(1), syn)
+    assert st == ST_NUMERIC and not np.isnan(out).any()
+    out, st = forward_models(emu, d, 0, 3, tiny, np.zeros(1), np.zeros_like(syn))
+    assert st == ST_UNRESOLVED and np.isfinite(out[0, 0]) and np.isneginf(out[0, 1:]).all()
+    out64, st64 = forward_models(emu, d, 0, 0, tiny, np.zeros(1), syn)
+    assert st64 == 0 and np.isfinite(out64).all()

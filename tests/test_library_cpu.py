@@ -83,3 +83,45 @@ def test_gemm_flops_are_part_of_the_counted_work(L, d, chi):
     assert 0 < i["gemm_flops"] < i["flops"]
     assert i["gemm_flops"] <= i["gemm_flops_syndrome"] <= 4 * i["gemm_flops"]
     assert i["gemm_flops_syndrome"] < i["flops_syndrome"]
+
+
+def test_status_entry_point_rejects_missing_workspace(L):
+    """tn_workspace_status needs a workspace of at least one header block."""
+    assert L.tn_workspace_status(None, 0, None, None) == _lib.TN_EINVAL
+    assert L.tn_last_error()
+
+
+@pytest.mark.parametrize("case", ["byte", "neg", "nan", "over", "index", "index_neg"])
+def test_input_value_checks_raise_before_launch(case):
+    """The host-side value check that runs before every checked launch: each
+    kind of invalid input raises ValueError (no kernel is launched); valid
+    inputs pass.  Runs on CPU tensors."""
+    import torch
+    import paper_2605_17230_amd as tn
+    import synth
+    d = 5
+    rates = torch.from_numpy(np.stack([synth.depolarizing(d, 0.1), synth.biased(d, 0.1, 10.0)]))
+    syn = torch.from_numpy(synth.sample(d, synth.depolarizing(d, 0.1), 8, seed=1)["syndromes"])
+    mi = torch.zeros(8, dtype=torch.int32)
+    tn.check_input_values(syn, rates, mi)
+    tn.check_input_values(syn, rates[0], None)
+    if case == "byte":
+        syn = syn.clone()
+        syn[3, 7] = 2
+    elif case == "neg":
+        rates = rates.clone()
+        rates[1, 4, 0] = -1e-9
+    elif case == "nan":
+        rates = rates.clone()
+        rates[0, 0, 2] = float("nan")
+    elif case == "over":
+        rates = rates.clone()
+        rates[0, 3] = torch.tensor([0.4, 0.4, 0.3], dtype=torch.float64)
+    elif case == "index":
+        mi = mi.clone()
+        mi[5] = 2
+    else:
+        mi = mi.clone()
+        mi[0] = -1
+    with pytest.raises(ValueError):
+        tn.check_input_values(syn, rates, mi)

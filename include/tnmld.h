@@ -187,8 +187,25 @@ int tn_set_tuning(int32_t d, int32_t chi, int32_t precision, int32_t group, int3
  * receives the number of cosets of strictly positive models written as
  * -INFINITY while another coset of their syndrome was finite (below the
  * form's resolution; not an error).  ws_bytes: size of the workspace
- * (>= 256). */
+ * (>= 256).  workspace = NULL reads the status of the last
+ * tn_decode_batch_noalloc call on the current device (ws_bytes ignored). */
 int tn_workspace_status(const void* workspace, size_t ws_bytes, void* stream, int64_t* unresolved_cosets);
+
+/* tn_decode_batch without a workspace, for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels and results (bit for bit), with
+ * their scratch in a fixed 128 MiB device array that the library holds on
+ * every device it runs on until the process ends; the contraction plans are
+ * copied into it from host memory on `stream` at every call.  The call makes
+ * no device allocation (no hipMalloc, hipFree or allocating library routine).
+ * Fewer persistent work-groups run when the usual count does not fit the
+ * array; a call whose segments need more than the array for a single
+ * work-group per launch (per work-group ~1.4 MB at d = 17, chi = 32) or more
+ * than 4 MiB of plans fails with TN_EINVAL before anything is enqueued.
+ * Every call on one device shares that device's array: calls that overlap on
+ * one device (two streams, two threads) race and must be serialised by the
+ * caller.  Status: tn_workspace_status(NULL, 0, stream, ...). */
+int tn_decode_batch_noalloc(const tn_segment* segs, int32_t nseg, double tie_tol, void* stream);
 
 /* Message for the last non-OK status returned on this thread. */
 const char* tn_last_error(void);

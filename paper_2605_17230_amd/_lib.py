@@ -62,6 +62,8 @@ def lib():
         L.tn_plan_gemm_flops.argtypes = [I32, I32, I32, ctypes.POINTER(D)]
         L.tn_set_tuning.restype = ctypes.c_int
         L.tn_set_tuning.argtypes = [I32, I32, I32, I32, I32]
+        L.tn_decode_batch_noalloc.restype = ctypes.c_int
+        L.tn_decode_batch_noalloc.argtypes = [seg_p, I32, D, P]
         L.tn_workspace_status.restype = ctypes.c_int
         L.tn_workspace_status.argtypes = [P, SZ, P, ctypes.POINTER(I64)]
         L.tn_last_error.restype = ctypes.c_char_p

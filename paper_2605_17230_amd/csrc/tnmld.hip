@@ -137,6 +137,11 @@ __global__ void decide_kernel(const double* logz, int64_t count, double tie_tol,
   if (cls) cls[b] = (uint8_t)c;
 }
 
+// Fixed device array of the allocation-free entry point (tn_decode_batch_noalloc),
+// 128 MiB on every device the library runs on, for the life of the process.
+constexpr size_t kNoAllocBytes = 128ull << 20;
+__device__ __align__(256) char scratch[kNoAllocBytes];
+
 // ------------------------------------------------------------------ host side
 namespace {
 
@@ -282,7 +287,10 @@ int choose_group(int d, int chi, int precision, int lds_limit, Plan* out, std::s
   return best_g;
 }
 
-int get_plan(int d, int chi, int precision, int lds_limit, DevPlan** out) {
+// Plans are kept per (device, d, chi, group).  upload = false: the plan is
+// built and kept on the host only (dev stays null), for the allocation-free
+// entry point, which copies the blob into its own fixed device array.
+int get_plan(int d, int chi, int precision, int lds_limit, DevPlan** out, bool upload = true) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(TN_EDEVICE, "no HIP device");
   Plan p;
@@ -292,22 +300,26 @@ int get_plan(int d, int chi, int precision, int lds_limit, DevPlan** out) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto key = std::make_tuple(dev, d, chi, g);
   auto it = g_plans.find(key);
-  if (it != g_plans.end()) {
+  if (it != g_plans.end() && (it->second->dev || !upload)) {
     *out = it->second;
     return TN_OK;
   }
-  DevPlan* dp = new DevPlan;
-  dp->plan = std::move(p);
-  if (hipMalloc(&dp->dev, dp->plan.blob.size()) != hipSuccess) {
-    delete dp;
-    return fail(TN_ENOMEM, "hipMalloc of plan failed");
+  DevPlan* dp = it != g_plans.end() ? it->second : new DevPlan;
+  if (it == g_plans.end()) {
+    dp->plan = std::move(p);
+    g_plans[key] = dp;
   }
-  if (hipMemcpy(dp->dev, dp->plan.blob.data(), dp->plan.blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(dp->dev);
-    delete dp;
+  if (!upload) {
+    *out = dp;
+    return TN_OK;
+  }
+  uint8_t* devp = nullptr;
+  if (hipMalloc(&devp, dp->plan.blob.size()) != hipSuccess) return fail(TN_ENOMEM, "hipMalloc of plan failed");
+  if (hipMemcpy(devp, dp->plan.blob.data(), dp->plan.blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(devp);
     return fail(TN_EDEVICE, "plan upload failed");
   }
-  g_plans[key] = dp;
+  dp->dev = devp;
   *out = dp;
   return TN_OK;
 }
@@ -348,6 +360,7 @@ bool small_plan(const PlanHeader& h, int precision) {
 constexpr int kMaxLaunches = 2 * (TN_FP32_PLAIN + 1);  // one per precision and size class
 
 struct Launch {
+  const Plan* host_plan[TN_MAX_SEGMENTS];  // plan of each job (host copy)
   bool small;      // 256-thread build
   bool aj_global;  // small launch whose MPO step reads the input site from its region (LDS)
   int precision;
@@ -372,7 +385,7 @@ unsigned* status_word(void* workspace) {
 
 // Build the launch groups (one per precision) and the workspace layout.
 int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vector<Launch>* out, size_t* ws_bytes,
-                  int* nwg, bool allow_small = true) {
+                  int* nwg, bool allow_small = true, bool upload = true) {
   int rc = validate(segs, nseg);
   if (rc) return rc;
   DevInfo di;
@@ -396,8 +409,9 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
       if (s.precision != prec || s.count == 0) continue;
       if (!precision_built(prec)) return fail(TN_EUNSUPPORTED, "precision not built");
       DevPlan* dp = nullptr;
-      if ((rc = get_plan(s.d, s.chi, prec, lds_limit, &dp))) return rc;
+      if ((rc = get_plan(s.d, s.chi, prec, lds_limit, &dp, upload))) return rc;
       if ((allow_small && small_plan(dp->plan.h, prec)) != small) continue;
+      L.host_plan[L.jt.n] = &dp->plan;
       JobDev& j = L.jt.j[L.jt.n++];
       j.plan = dp->dev;
       j.rates = s.rates;
@@ -456,27 +470,18 @@ int launch_fwd(const Launch& L, int nwg, char* ws_scratch, unsigned long long* c
   return TN_OK;
 }
 
-int run_forward(const tn_segment* segs, int32_t nseg, void* workspace, size_t ws_bytes, void* stream) {
-  std::vector<Launch> launches;
-  size_t need = 0;
-  int nwg = 0;
-  DevInfo di;
-  int rc = validate(segs, nseg);
-  if (rc) return rc;
-  if ((rc = device_info(&di))) return rc;
-  if ((rc = plan_launches(segs, nseg, std::min(di.lds_max, kLdsLimit), &launches, &need, &nwg))) return rc;
-  if (launches.empty()) return TN_OK;
-  if (!workspace || ws_bytes < need) return fail(TN_EINVAL, "workspace too small: need " + std::to_string(need));
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  char* base = reinterpret_cast<char*>(workspace);
-  size_t off = align_up(sizeof(unsigned long long) * kMaxLaunches);
-  unsigned* status = status_word(workspace);
+// Enqueue the planned launches.  header: workspace header (counters and
+// status word); regions: start of the per-work-group regions, launch after
+// launch (nwg of each x its aligned per-group bytes).
+int enqueue_forward(std::vector<Launch>& launches, char* header, char* regions, hipStream_t st) {
+  unsigned* status = status_word(header);
   zero_status<<<1, 64, 0, st>>>(status);
-  int li = 0;
+  size_t off = 0;
+  int li = 0, rc = TN_OK;
   for (auto& L : launches) {
     for (int i = 0; i < L.jt.n; ++i) L.jt.j[i].status = status;
-    unsigned long long* counter = reinterpret_cast<unsigned long long*>(base) + li;
-    char* scr = base + off;
+    unsigned long long* counter = reinterpret_cast<unsigned long long*>(header) + li;
+    char* scr = regions + off;
     off += (size_t)L.nwg * align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
     if (L.small) {
       const LdsLayout lay = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision), L.aj_global);
@@ -495,6 +500,105 @@ int run_forward(const tn_segment* segs, int32_t nseg, void* workspace, size_t ws
     ++li;
   }
   return TN_OK;
+}
+
+int run_forward(const tn_segment* segs, int32_t nseg, void* workspace, size_t ws_bytes, void* stream) {
+  std::vector<Launch> launches;
+  size_t need = 0;
+  int nwg = 0;
+  DevInfo di;
+  int rc = validate(segs, nseg);
+  if (rc) return rc;
+  if ((rc = device_info(&di))) return rc;
+  if ((rc = plan_launches(segs, nseg, std::min(di.lds_max, kLdsLimit), &launches, &need, &nwg))) return rc;
+  if (launches.empty()) return TN_OK;
+  if (!workspace || ws_bytes < need) return fail(TN_EINVAL, "workspace too small: need " + std::to_string(need));
+  char* base = reinterpret_cast<char*>(workspace);
+  return enqueue_forward(launches, base, base + align_up(sizeof(unsigned long long) * kMaxLaunches),
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+// ---- allocation-free entry point ---------------------------------------------
+// Device memory of tn_decode_batch_noalloc: a fixed array that every device the
+// library runs on holds for the life of the process.  Layout: workspace header
+// (kAlign bytes), the plan blobs of the call (kNoAllocPlanBytes), then the
+// per-work-group regions.  Host code never passes `scratch` itself to a kernel
+// or a copy: it uses the device address that hipGetSymbolAddress returned for
+// the current device (noalloc_base).
+constexpr size_t kNoAllocPlanBytes = 4ull << 20;
+
+std::mutex g_noalloc_mu;
+std::map<int, char*> g_noalloc_base;  // device -> address of `scratch` on that device
+
+int noalloc_base(char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(TN_EDEVICE, "no HIP device");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  auto it = g_noalloc_base.find(dev);
+  if (it == g_noalloc_base.end()) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+      return fail(TN_EDEVICE, "hipGetSymbolAddress of the fixed scratch array failed");
+    it = g_noalloc_base.emplace(dev, reinterpret_cast<char*>(p)).first;
+  }
+  *out = it->second;
+  return TN_OK;
+}
+
+int run_forward_noalloc(const tn_segment* segs, int32_t nseg, void* stream) {
+  std::vector<Launch> launches;
+  size_t need = 0;
+  int nwg = 0;
+  DevInfo di;
+  int rc = validate(segs, nseg);
+  if (rc) return rc;
+  if ((rc = device_info(&di))) return rc;
+  char* base = nullptr;
+  if ((rc = noalloc_base(&base))) return rc;
+  if ((rc = plan_launches(segs, nseg, std::min(di.lds_max, kLdsLimit), &launches, &need, &nwg, true, false)))
+    return rc;
+  if (launches.empty()) return TN_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // plan blobs (one copy per distinct plan) after the header
+  std::map<const Plan*, size_t> placed;
+  size_t pofs = 0;
+  for (auto& L : launches)
+    for (int i = 0; i < L.jt.n; ++i) {
+      const Plan* p = L.host_plan[i];
+      auto it = placed.find(p);
+      if (it == placed.end()) {
+        if (pofs + align_up(p->blob.size()) > kNoAllocPlanBytes)
+          return fail(TN_EINVAL, "plans of this call exceed the allocation-free entry point's plan area");
+        it = placed.emplace(p, pofs).first;
+        pofs += align_up(p->blob.size());
+      }
+      L.jt.j[i].plan = reinterpret_cast<const uint8_t*>(base + kAlign + it->second);
+    }
+  // persistent work-groups: as many as the fixed regions hold, up to the usual count
+  const size_t avail = kNoAllocBytes - kAlign - kNoAllocPlanBytes;
+  size_t per_round = 0, full = 0;
+  for (auto& L : launches) {
+    const size_t pw = align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
+    per_round += pw;
+    full += (size_t)L.nwg * pw;
+  }
+  if (per_round > avail)
+    return fail(TN_EINVAL, "one work-group of each launch needs " + std::to_string(per_round) +
+                               " bytes; the allocation-free entry point holds " + std::to_string(avail));
+  if (full > avail) {
+    const double f = (double)avail / (double)full;
+    for (auto& L : launches) {
+      const size_t pw = align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
+      int w = (int)((double)L.nwg * f);
+      L.nwg = std::max(1, std::min(L.nwg, w));
+      (void)pw;
+    }
+  }
+  for (const auto& kv : placed)
+    if (hipMemcpyAsync(base + kAlign + kv.second, kv.first->blob.data(), kv.first->blob.size(),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+      return fail(TN_EDEVICE, "plan copy failed");
+  return enqueue_forward(launches, base, base + kAlign + kNoAllocPlanBytes, st);
 }
 
 // Layout of the backward call: one launch (all segments share a precision).
@@ -645,6 +749,19 @@ int tn_decode_batch(const tn_segment* segs, int32_t nseg, double tie_tol, void* 
   return TN_OK;
 }
 
+int tn_decode_batch_noalloc(const tn_segment* segs, int32_t nseg, double tie_tol, void* stream) {
+  if (!(tie_tol > 0.0)) tie_tol = 1e-9;
+  int rc = run_forward_noalloc(segs, nseg, stream);
+  if (rc) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  for (int i = 0; i < nseg; ++i)
+    if (segs[i].count > 0 && (segs[i].out_logp || segs[i].out_class))
+      decide_kernel<<<(unsigned)((segs[i].count + 255) / 256), 256, 0, st>>>(segs[i].out_logz, segs[i].count, tie_tol,
+                                                                           segs[i].out_logp, segs[i].out_class);
+  if (hipGetLastError() != hipSuccess) return fail(TN_EDEVICE, "decide launch failed");
+  return TN_OK;
+}
+
 int tn_coset_loglik_backward(const tn_segment* segs, int32_t nseg, const double* const* grad_logp,
                              double* const* grad_log_rates, int32_t forward_done, void* workspace, size_t ws_bytes,
                              void* stream) {
@@ -760,7 +877,13 @@ int tn_set_tuning(int32_t d, int32_t chi, int32_t precision, int32_t group, int3
 }
 
 int tn_workspace_status(const void* workspace, size_t ws_bytes, void* stream, int64_t* unresolved_cosets) {
-  if (!workspace || ws_bytes < kAlign) return fail(TN_EINVAL, "workspace too small for a status word");
+  if (!workspace) {  // the allocation-free entry point's fixed array on the current device
+    char* base = nullptr;
+    if (int rc = noalloc_base(&base)) return rc;
+    workspace = base;
+    ws_bytes = kAlign;
+  }
+  if (ws_bytes < kAlign) return fail(TN_EINVAL, "workspace too small for a status word");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (hipStreamSynchronize(st) != hipSuccess) return fail(TN_EDEVICE, "stream synchronisation failed");
   unsigned v[4] = {0u, 0u, 0u, 0u};

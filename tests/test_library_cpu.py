@@ -85,10 +85,16 @@ def test_gemm_flops_are_part_of_the_counted_work(L, d, chi):
     assert i["gemm_flops_syndrome"] < i["flops_syndrome"]
 
 
-def test_status_entry_point_rejects_missing_workspace(L):
-    """tn_workspace_status needs a workspace of at least one header block."""
-    assert L.tn_workspace_status(None, 0, None, None) == _lib.TN_EINVAL
+def test_status_entry_point_rejects_small_workspace(L):
+    """tn_workspace_status needs a workspace of at least one header block
+    (a NULL workspace names the allocation-free entry point's array, which
+    needs a device)."""
+    buf = ctypes.create_string_buffer(64)
+    assert L.tn_workspace_status(buf, 64, None, None) == _lib.TN_EINVAL
     assert L.tn_last_error()
+    import torch
+    if not torch.cuda.is_available():
+        assert L.tn_workspace_status(None, 0, None, None) == _lib.TN_EDEVICE
 
 
 @pytest.mark.parametrize("case", ["byte", "neg", "nan", "over", "index", "index_neg"])

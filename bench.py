@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16")
     ap.add_argument("--compare", default="fp32plain", help="second form timed once ('' to skip)")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5", "fit", "study"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5", "fit", "study", "planar"])
     ap.add_argument("--study-count", type=int, default=4096, help="syndromes per (d, p) point of the study")
     ap.add_argument("--fit-steps", type=int, default=60, help="Adam steps of the fit workload")
     ap.add_argument("--fit-batch", type=int, default=1024, help="syndromes per step of the fit workload")
@@ -250,6 +250,67 @@ def bench_study(a, torch, tn, synth, dev):
     print(json.dumps(out), flush=True)
 
 
+PEAK_MFMA_FP64_TFLOPS = 78.6  # dense FP64 matrix peak of the MI355X (equal to the FP64 vector peak)
+
+
+def bench_planar(a, torch, tn, synth, dev, stream):
+    """Planar exact solver under bit-flip noise: d = 17, p = 0.10, 16,384
+    seeded syndromes (two 580 x 580 complex LU factorisations per syndrome),
+    against the boundary-MPS path on the same syndromes and the oracle."""
+    import oracle
+    d, p, n = 17, 0.10, a.count
+    rates = synth.bitflip(d, p)
+    smp = synth.sample(d, rates, n, 3100)
+    syn, rt = torch.from_numpy(smp["syndromes"]).to(dev), torch.from_numpy(rates).to(dev)
+    info = tn.bitflip_plan_info(d)
+    print("bench: planar exact solver d=%d bit-flip p=%.2f, %d syndromes" % (d, p, n), file=sys.stderr, flush=True)
+    for _ in range(a.warmup):
+        tn.decode_bitflip(syn, rt, d)
+    torch.cuda.synchronize()
+    ev = []
+    for _ in range(a.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lz, lp, cls = tn.decode_bitflip(syn, rt, d)
+        e1.record(stream)
+        ev.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = float(np.mean([x.elapsed_time(y) for x, y in ev]))
+    flops = 2.0 * n * info["lu_flops"]  # two cosets; complex LU, leading term (8/3) N^3
+    ach = flops / (ms / 1e3) / 1e12
+    lp = lp.cpu().numpy()
+    cls = cls.cpu().numpy()
+    out = {
+        "metric": "syndromes/s of exact decoding under bit-flip noise at d=17 (planar Kac-Ward solver)",
+        "value": n / (ms / 1e3), "unit": "syndromes/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "rotated surface code d=17, bit-flip p=0.10, %d seeded syndromes, exact" % n},
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_MFMA_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach / PEAK_MFMA_FP64_TFLOPS, "traffic": None, "flops_per_launch": flops,
+                     "kernel": "kw_kernel"},
+        "logical_error_rate": float((cls != smp["true_class"]).mean()),
+    }
+    ns = min(512, n)
+    with __import__("warnings").catch_warnings():
+        __import__("warnings").simplefilter("ignore")
+        _, mlp, mcls = tn.decode(syn[:ns], rt, d, 32, "bf16")
+    out["vs_boundary_mps_bf16_chi32"] = {"syndromes": ns,
+                                         "max_abs_dlogp": float(np.max(np.abs(mlp.cpu().numpy() - lp[:ns]))),
+                                         "class_agreement": float((mcls.cpu().numpy() == cls[:ns]).mean())}
+    if not a.no_cpu:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        k = max(threads, 1)
+        t0 = time.time()
+        ref = oracle.transfer(d, rates, smp["syndromes"][:k], threads=threads)
+        dt = time.time() - t0
+        out["cpu_baseline"] = {"value": k / dt, "unit": "syndromes/s", "cores": threads, "kind": "oracle",
+                               "sample": "first %d syndromes, exact FP64 transfer-matrix contraction, %.1f s" % (k, dt)}
+        out["parity_vs_oracle"] = {"syndromes": k, "max_abs_dlogp": float(np.max(np.abs(
+            np.logaddexp.reduce(ref, 1) - lp[:k])))}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -274,6 +335,9 @@ def main():
         return
     if a.workload == "study":
         bench_study(a, torch, tn, synth, dev)
+        return
+    if a.workload == "planar":
+        bench_planar(a, torch, tn, synth, dev, stream)
         return
     if a.workload == "c3":
         rates = synth.depolarizing(D, P)

@@ -207,6 +207,40 @@ int tn_workspace_status(const void* workspace, size_t ws_bytes, void* stream, in
  * caller.  Status: tn_workspace_status(NULL, 0, stream, ...). */
 int tn_decode_batch_noalloc(const tn_segment* segs, int32_t nseg, double tie_tol, void* stream);
 
+/* ---- Planar exact solver for bit-flip noise (paper Sec. 3.1.3) ------------
+ * Under bit-flip noise (p_Y = p_Z = 0 for every qubit) each coset partition
+ * function is the partition function of a random-bond Ising model on the
+ * planar graph of X-type checks (Sec. 3.1.1, eq. "rbim"), which the Kac-Ward
+ * determinant gives exactly in O(|E|^3): Z_l(s) = 2^(m_X - n) sqrt(det(I -
+ * Lambda)), with Lambda the 2(n+1) x 2(n+1) complex matrix over the directed
+ * bonds (weights t_q = +-(1 - 2 p_q), the sign from the coset's reference
+ * error, times the phase of the turning angle between consecutive bonds).
+ * The logical X coset flips the signs along a logical representative; the Y
+ * and Z cosets are impossible (log Z = -INFINITY), as is every coset when an
+ * X-type check fired.  Computed in FP64 (dense LU with partial pivoting; the
+ * trailing updates on the FP64 matrix cores). */
+
+/* Bytes of device workspace tn_bitflip_decode needs for these segments
+ * (precision must be TN_FP64; chi is ignored).  0 on invalid arguments. */
+size_t tn_bitflip_workspace_size(const tn_segment* segs, int32_t nseg);
+
+/* Exact log Z_l(s) (l = I, X, Y, Z; Y and Z are -INFINITY), log P(s) and the
+ * tie-tolerant class (as tn_decode_batch) for bit-flip noise.  segs: HOST
+ * array of nseg <= TN_MAX_SEGMENTS descriptors; each segment's rates must have
+ * p_Y = p_Z = 0 (a syndrome whose model violates that, or has p_X outside
+ * [0, 1], is written as -INFINITY and recorded for tn_workspace_status as
+ * TN_EINVAL); precision must be TN_FP64 (else TN_EINVAL); chi is ignored.
+ * workspace: device, ws_bytes >= tn_bitflip_workspace_size(segs, nseg),
+ * caller-owned; about (2(d^2+1))^2 x 16 bytes per persistent work-group. */
+int tn_bitflip_decode(const tn_segment* segs, int32_t nseg, double tie_tol, void* workspace, size_t ws_bytes,
+                      void* stream);
+
+/* HOST helper: properties of the planar solver's plan at distance d:
+ * info[0] matrix order 2(d^2+1), info[1] non-zero entries of Lambda,
+ * info[2] real flops of one complex LU (8/3 N^3), info[3] scratch bytes per
+ * work-group, info[4] (m_X - n) ln 2.  info: host array of >= 5 doubles. */
+int tn_bitflip_plan_info(int32_t d, double* info);
+
 /* Message for the last non-OK status returned on this thread. */
 const char* tn_last_error(void);
 

@@ -4,9 +4,9 @@ The contraction runs in ``libtnmld.so`` (HIP, gfx950); this package only
 marshals arguments.  See include/tnmld.h for the C ABI.
 """
 from ._lib import TNError, lib, LIB_PATH  # noqa: F401
-from .api import (SegmentInput, SegmentOutput, check_input_values, code_stabilizers, coset_loglik,  # noqa: F401
-                  coset_loglik_backward, decode, decode_segments, log_posterior, plan_info, set_tuning,
-                  workspace_bytes)
+from .api import (SegmentInput, SegmentOutput, bitflip_plan_info, check_input_values, code_stabilizers,  # noqa: F401
+                  coset_loglik, coset_loglik_backward, decode, decode_bitflip, decode_bitflip_segments, decode_segments,
+                  log_posterior, plan_info, set_tuning, workspace_bytes)
 from .fit import fit_log_rates  # noqa: F401
 
 from . import tune as _tune  # noqa: E402
@@ -17,5 +17,6 @@ except Exception:  # a missing or unreadable cache keeps the defaults
     pass
 
 __all__ = ["TNError", "SegmentInput", "SegmentOutput", "coset_loglik", "coset_loglik_backward", "log_posterior",
-           "decode", "decode_segments", "check_input_values", "workspace_bytes", "fit_log_rates", "plan_info",
+           "decode", "decode_segments", "decode_bitflip", "decode_bitflip_segments", "bitflip_plan_info",
+           "check_input_values", "workspace_bytes", "fit_log_rates", "plan_info",
            "set_tuning", "code_stabilizers", "lib", "LIB_PATH"]

@@ -64,6 +64,12 @@ def lib():
         L.tn_set_tuning.argtypes = [I32, I32, I32, I32, I32]
         L.tn_decode_batch_noalloc.restype = ctypes.c_int
         L.tn_decode_batch_noalloc.argtypes = [seg_p, I32, D, P]
+        L.tn_bitflip_workspace_size.restype = SZ
+        L.tn_bitflip_workspace_size.argtypes = [seg_p, I32]
+        L.tn_bitflip_decode.restype = ctypes.c_int
+        L.tn_bitflip_decode.argtypes = [seg_p, I32, D, P, SZ, P]
+        L.tn_bitflip_plan_info.restype = ctypes.c_int
+        L.tn_bitflip_plan_info.argtypes = [I32, ctypes.POINTER(D)]
         L.tn_workspace_status.restype = ctypes.c_int
         L.tn_workspace_status.argtypes = [P, SZ, P, ctypes.POINTER(I64)]
         L.tn_last_error.restype = ctypes.c_char_p

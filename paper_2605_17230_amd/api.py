@@ -321,6 +321,61 @@ def log_posterior(log_rates, syndromes, d, chi, precision="fp32", model_index=No
     return _LogPosterior.apply(log_rates, syndromes, model_index, d, chi, precision)
 
 
+def _bitflip_rates(rates, n):
+    r = rates.to(torch.float64)
+    if r.dim() == 1:  # p_X per qubit
+        r = torch.stack([r, torch.zeros_like(r), torch.zeros_like(r)], -1)
+    if r.dim() == 2:
+        r = r.unsqueeze(0)
+    if r.shape[1:] != (n, 3):
+        raise ValueError("bit-flip rates must be [d*d] (p_X), [d*d, 3] or [M, d*d, 3]")
+    return r.contiguous()
+
+
+def decode_bitflip_segments(segs, tie_tol: float = 1e-9, stream=None, workspace_buf=None, check: bool = True):
+    """Exact decoding under bit-flip noise by the planar (Kac-Ward) solver.
+
+    segs: SegmentInput list (chi and precision are ignored; the solver runs in
+    FP64); rates may be p_X per qubit [d*d].  Returns SegmentOutput per
+    segment: log Z (Y and Z cosets -inf), log P(s), class.  check: as for
+    decode_segments (the host check also requires p_Y = p_Z = 0)."""
+    capturing = torch.cuda.is_current_stream_capturing()
+    do_check = bool(check) and not capturing
+    conv = []
+    for s in segs:
+        _need_cuda(s.rates, "rates")
+        r = _bitflip_rates(s.rates, s.d * s.d)
+        if do_check and check != "device" and bool((r[..., 1:] != 0).any()):
+            raise ValueError("the planar solver needs bit-flip noise: p_Y = p_Z = 0")
+        conv.append(SegmentInput(s.d, 0, s.syndromes, r, s.model_index, "fp64"))
+    arr, outs, keep = _prepare(conv, do_check and check != "device")
+    L = lib()
+    nbytes = L.tn_bitflip_workspace_size(arr, len(conv))
+    if nbytes == 0:
+        check_rc(_lib.TN_EINVAL)
+    dev = conv[0].syndromes.device
+    ws = _pick_workspace(workspace_buf, nbytes, dev, stream)
+    st = _launch_stream(stream, dev, keep, outs)
+    check_rc(L.tn_bitflip_decode(arr, len(conv), float(tie_tol), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                 ctypes.c_void_p(st)))
+    if do_check:
+        _check_status(ws, st)
+    del keep
+    return outs
+
+
+def decode_bitflip(syndromes, rates, d, model_index=None, tie_tol=1e-9):
+    """(logz [B,4], logp [B], class [B]) under bit-flip noise, exactly."""
+    o = decode_bitflip_segments([SegmentInput(d, 0, syndromes, rates, model_index, "fp64")], tie_tol)[0]
+    return o.logz, o.logp, o.cls
+
+
+def bitflip_plan_info(d):
+    info = (ctypes.c_double * 5)()
+    check_rc(lib().tn_bitflip_plan_info(d, info))
+    return dict(order=int(info[0]), nnz=int(info[1]), lu_flops=info[2], scratch_bytes=info[3], log_pref=info[4])
+
+
 def plan_info(d, chi, precision="fp32"):
     info = (ctypes.c_double * 8)()
     check_rc(lib().tn_plan_info(d, chi, PRECISIONS[precision], info))

@@ -22,6 +22,7 @@
 // the device from per-qubit rates and the reference error), the MPS bond
 // dimensions before/after truncation and the scratch / LDS sizes.
 #pragma once
+#include <cstddef>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -125,6 +126,12 @@ struct LdsLayout {
 };
 
 inline int32_t pad64b(int64_t x) { return (int32_t)((x + 63) / 64 * 64); }
+
+// Caller workspace header (the first kWorkspaceAlign bytes of every workspace):
+// work counters from byte 0, the status word of the last call at
+// kStatusOffset (ST_* bits) and its 64-bit count of unresolved cosets 8 bytes on.
+constexpr size_t kWorkspaceAlign = 256;
+constexpr size_t kStatusOffset = 128;
 
 // aj_global: the MPO step reads the input site tensor from its scratch region
 // instead of an LDS copy (o.Aj = -1), to fit two work-groups of the 256-thread

@@ -137,6 +137,15 @@ __global__ void decide_kernel(const double* logz, int64_t count, double tie_tol,
   if (cls) cls[b] = (uint8_t)c;
 }
 
+// Host helpers shared with the planar exact solver (kacward.hip).
+int report_error(int code, const std::string& msg);
+void launch_zero_status(unsigned* st, hipStream_t stream) { zero_status<<<1, 64, 0, stream>>>(st); }
+void launch_decide(const double* logz, int64_t count, double tie_tol, double* logp, uint8_t* cls,
+                   hipStream_t stream) {
+  if (count > 0 && (logp || cls))
+    decide_kernel<<<(unsigned)((count + 255) / 256), 256, 0, stream>>>(logz, count, tie_tol, logp, cls);
+}
+
 // Fixed device array of the allocation-free entry point (tn_decode_batch_noalloc),
 // 128 MiB on every device the library runs on, for the life of the process.
 constexpr size_t kNoAllocBytes = 128ull << 20;
@@ -371,13 +380,13 @@ struct Launch {
   int nwg;  // persistent work-groups of this launch
 };
 
-constexpr size_t kAlign = 256;
+constexpr size_t kAlign = kWorkspaceAlign;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace header (the first kAlign bytes): one work counter per launch, then
 // the status word of the last call (ST_* bits, read by tn_workspace_status)
 // and, 8 bytes on, its 64-bit count of unresolved cosets.
-constexpr size_t kStatusOfs = 128;
+constexpr size_t kStatusOfs = kStatusOffset;
 static_assert(sizeof(unsigned long long) * kMaxLaunches <= kStatusOfs, "header layout");
 unsigned* status_word(void* workspace) {
   return reinterpret_cast<unsigned*>(reinterpret_cast<char*>(workspace) + kStatusOfs);
@@ -701,6 +710,9 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
 }
 
 }  // namespace
+
+int report_error(int code, const std::string& msg) { return fail(code, msg); }
+
 }  // namespace tnmld
 
 using namespace tnmld;

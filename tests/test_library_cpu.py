@@ -131,3 +131,25 @@ def test_input_value_checks_raise_before_launch(case):
         mi[0] = -1
     with pytest.raises(ValueError):
         tn.check_input_values(syn, rates, mi)
+
+
+@pytest.mark.parametrize("d", [3, 5, 9, 17, 31])
+def test_planar_plan_counts(d):
+    """The Kac-Ward plan: matrix order 2(n + 1) (a bond per qubit and the ghost
+    bond, both directions); the entries of Lambda are the pairs of bonds
+    meeting at a vertex, sum over vertices of deg (deg - 1), with the degrees
+    counted here from the check layout (an X-type check has one bond per qubit
+    of its support; each ghost has the d qubits of its side plus the ghost
+    bond); the prefactor (m_X - n) ln 2."""
+    import paper_2605_17230_amd as tn
+    import synth
+    info = tn.bitflip_plan_info(d)
+    n = d * d
+    types, sup = synth.code_checks(d)
+    deg = [int((s >= 0).sum()) for t, s in zip(types, sup) if t == 0]
+    deg += [d + 1, d + 1]
+    assert info["order"] == 2 * (n + 1)
+    assert info["nnz"] == sum(k * (k - 1) for k in deg)
+    assert abs(info["log_pref"] - ((n - 1) // 2 - n) * np.log(2.0)) < 1e-12
+    with pytest.raises(tn.TNError):
+        tn.bitflip_plan_info(4)

@@ -126,20 +126,24 @@ int tn_decode_batch(const tn_segment* segs, int32_t nseg, double tie_tol, void* 
 /* Gradient of the weighted log-likelihood  sum_b grad_logp[b] * log P(s_b)
  * (the per-syndrome term of the paper's eq. "dmle_loss") with respect to
  * theta_{q,P} = ln p_{q,P}, P in {X, Y, Z}, p_I = 1 - p_X - p_Y - p_Z.
- * Contracts each syndrome's cosets forward with row checkpoints (the rows
- * common to the four cosets once), recomputes each segment of rows from its
- * checkpoint, sweeps a second boundary MPS up from the bottom, and contracts
- * the environment of every qubit tensor.
+ * One work-group per syndrome contracts its cosets top-down (the rows common
+ * to the four cosets once), storing the boundary MPS before every row, takes
+ * the coset weights grad_logp[b] * P(l|s) from the log Z values of that sweep,
+ * then sweeps a second boundary MPS up from the bottom for every coset with
+ * a non-zero weight and contracts the environment of every qubit tensor
+ * against the stored top states (no recomputation).
  * grad_logp[s]: device [count] of segment s; grad_log_rates[s]: device
  * [n_models][d*d][3], ACCUMULATED (+=) in FP64 by a deterministic reduction.
- * forward_done = 0: the call first runs the forward pass and writes out_logz /
- * out_logp of each segment (out_logp must be non-NULL).  forward_done = 1:
- * out_logz / out_logp already hold the forward results for exactly these
- * inputs (e.g. from tn_decode_batch); they are read, not recomputed.
+ * forward_done = 0: the call also writes out_logz / out_logp of each segment
+ * (from its own top-down sweep; out_logp must be non-NULL).  forward_done = 1:
+ * the caller already holds the forward results (e.g. from tn_decode_batch);
+ * out_logz / out_logp are left as they are.  The gradient is the same, bit
+ * for bit, either way.
  * All segments of one call share one precision (else TN_EUNSUPPORTED).  Each
  * work-group walks a fixed stride of items, so the result is bitwise
  * reproducible for a given device and launch shape.
- * workspace: ws_bytes >= tn_workspace_size(segs, nseg, 1). */
+ * workspace: ws_bytes >= tn_workspace_size(segs, nseg, 1): the stored states
+ * take (S + 4 (2d - 1 - S)) boundary states per work-group, S = d - 1. */
 int tn_coset_loglik_backward(const tn_segment* segs, int32_t nseg, const double* const* grad_logp,
                              double* const* grad_log_rates, int32_t forward_done, void* workspace, size_t ws_bytes,
                              void* stream);

@@ -21,15 +21,31 @@ namespace tnmld {
 // row's input), bot: Phi_u in site regions (dims of the bottom-up row's
 // input).  Accumulates weight * d log Z / d theta into part[q*3 + k].
 // Returns false when the sandwich value <Phi_u| T_u |Psi_{u-1}> vanished
-// (nothing is added).
+// (nothing is added).  The contraction temporaries, the two site tensors
+// and the environment bonds of the current site are staged in LDS when the
+// layout has room for them (lay.gP, gA, gF, gE, gR >= 0: the storage of the
+// row steps, idle between them), else they live in the global P1..P3.
 template <typename Real>
 __device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsite, const uint8_t* codes,
                              const double* rates, const uint8_t* fbits, const Real* top, const Real* bot,
-                             const int64_t* region, Real* env, Real* P1, Real* P2, Real* P3, Real* Wv,
-                             double weight, double* part) {
+                             const int64_t* region, Real* env, Real* P1g, Real* P2g, Real* P3g, Real* Wv,
+                             double weight, double* part, uint8_t* smem, const LdsLayout& lay,
+                             int64_t tmp_elems) {
   const int tid = threadIdx.x;
+  Real* P1 = lay.gP >= 0 ? reinterpret_cast<Real*>(smem + lay.gP) : P1g;
+  Real* P2 = lay.gP >= 0 ? P1 + tmp_elems : P2g;
+  Real* P3 = lay.gP >= 0 ? P2 + tmp_elems : P3g;
+  const bool stage = lay.gA >= 0;
+  Real* sA = stage ? reinterpret_cast<Real*>(smem + lay.gA) : nullptr;
+  Real* sF = stage ? reinterpret_cast<Real*>(smem + lay.gF) : nullptr;
+  Real* sE = stage ? reinterpret_cast<Real*>(smem + lay.gE) : nullptr;
+  Real* sR = stage ? reinterpret_cast<Real*>(smem + lay.gR) : nullptr;
+  auto copy_in = [&](Real* dst, const Real* src, int cnt) {
+    for (int e = tid; e < cnt; e += NT) dst[e] = src[e];
+  };
   // offsets: top sites (compact), left environments E_J (J = 0..nsite), right R_J
   __shared__ int64_t s_toff[64], s_eoff[65], s_roff[65];
+  __shared__ double s_dw[64];
   if (tid == 0) {
     int64_t o = 0, e = 0;
     for (int J = 0; J < nsite; ++J) {
@@ -58,10 +74,14 @@ __device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
       else if (c >= W_PAULI) v = pauli_weight<Real>(rates + 3 * st.q, fbits[st.q], c - W_PAULI);
       Wv[tid] = v;
     }
-    __syncthreads();
   };
   // physical dimensions are 1, 2 or 4 and MPO bonds 1 or 2: index splits are shifts
   auto lg = [](int x) { return x == 4 ? 2 : (x == 2 ? 1 : 0); };
+  // bond sizes of the environment at bond J (left of site J)
+  auto envb = [&](int J) {
+    const int dt = J < nsite ? frow[J].Dl_old : 1, a = J < nsite ? frow[J].A : 1, db = J < nsite ? brow[J].Dl_old : 1;
+    return dt * a * db;
+  };
   // --- left environments ---------------------------------------------------
   if (tid == 0) env[s_eoff[0]] = Real(1);
   __syncthreads();
@@ -74,6 +94,15 @@ __device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
     const Real* E = env + s_eoff[J];
     Real* En = env + s_eoff[J + 1];
     load_w(st);
+    if (stage) {
+      copy_in(sA, Aj, DlA * qi * DrA);
+      copy_in(sF, Fj, DlF * qo * DrF);
+      copy_in(sE, E, envb(J));
+      Aj = sA;
+      Fj = sF;
+      E = sE;
+    }
+    __syncthreads();
     const int lqi = lg(qi), lqo = lg(qo), lB = lg(B);
     // P1[a][lF][si][rA] = sum_lA E[lA][a][lF] A[lA][si][rA]
     for_2d(Aa * DlF * qi, DrA, [&](int row, int rA) {
@@ -118,6 +147,17 @@ __device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
     const Real* E = env + s_eoff[J];
     Real* Rn = env + s_roff[J];
     load_w(st);
+    if (stage) {
+      copy_in(sA, Aj, DlA * qi * DrA);
+      copy_in(sF, Fj, DlF * qo * DrF);
+      copy_in(sR, R, envb(J + 1));
+      copy_in(sE, E, envb(J));
+      Aj = sA;
+      Fj = sF;
+      R = sR;
+      E = sE;
+    }
+    __syncthreads();
     const int lqi = lg(qi), lqo = lg(qo), lB = lg(B), lA_ = lg(Aa);
     // P1r[lF][so][rA][b] = sum_rF F[lF][so][rF] R[rA][b][rF]
     for_2d(DlF * qo, DrA * B, [&](int row, int col) {
@@ -136,15 +176,23 @@ __device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
         P3[row * DrA + rA] = acc;
       });
       __syncthreads();
-      // G[a][si][so][b] = sum_{lF,rA} P3[a][lF][si][rA] P1r[lF][so][rA][b], divided by the sandwich value
+      // G[a][si][so][b] = sum_{lF,rA} P3[a][lF][si][rA] P1r[lF][so][rA][b] / (sandwich value):
+      // 8 lanes per entry split the (lF, rA) sum and add their parts in a fixed order
       const int ng = Aa * qi * qo * B;
-      for (int e = tid; e < ng; e += NT) {
-        const int b = e & (B - 1), so = (e >> lB) & (qo - 1), si = (e >> (lB + lqo)) & (qi - 1), a = e >> (lB + lqo + lqi);
+      const int len = DlF * DrA;
+      for (int e0 = 0; e0 < ng; e0 += NT / 8) {
+        const int e = e0 + tid / 8, sub = tid & 7;
         double acc = 0;
-        for (int lF = 0; lF < DlF; ++lF)
-          for (int rA = 0; rA < DrA; ++rA)
+        if (e < ng) {
+          const int b = e & (B - 1), so = (e >> lB) & (qo - 1), si = (e >> (lB + lqo)) & (qi - 1),
+                    a = e >> (lB + lqo + lqi);
+          for (int x = sub; x < len; x += 8) {
+            const int lF = x / DrA, rA = x - lF * DrA;
             acc += (double)P3[((a * DlF + lF) * qi + si) * DrA + rA] * (double)P1[((lF * qo + so) * DrA + rA) * B + b];
-        P2[e] = Real(acc / S);
+          }
+        }
+        acc = group_sum(acc, 8);
+        if (e < ng && sub == 0) s_dw[e] = acc / S;
       }
       __syncthreads();
       if (tid == 0) {
@@ -152,7 +200,7 @@ __device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
         double dw[4] = {0, 0, 0, 0};
         for (int e = 0; e < ng; ++e) {
           const int c = codes[st.wofs + e];
-          if (c >= W_PAULI) dw[c - W_PAULI] += (double)P2[e];
+          if (c >= W_PAULI) dw[c - W_PAULI] += s_dw[e];
         }
         // wtab[P] = p(f xor P): d/dp[E] = d/dwtab[E xor f]
         const int fb = fbits[st.q];
@@ -188,24 +236,24 @@ __device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
   return true;
 }
 
-// Backward of syndrome b over its four cosets: adds, for each coset mlog,
-// weight_mlog * d log Z_mlog / d theta to part (FP64, [n][3]) where
-// weight = grad_logp[b] * P(l|s).  The rows before H->shared_rows are the same
-// for the four cosets (as in the forward pass), so the top-down sweep over them
-// and its checkpoints are computed once and the MPS after them is kept in
-// snap; each coset continues from it.  Segments of kseg rows that lie within
-// the shared rows recompute the same top states for every coset: they are
-// kept from the first coset that needs them.  Scratch layout (in Real
-// elements): top regions | bottom regions | K-row checkpoints | segment
-// states | environments | three temporaries | snapshot | shared segment
-// states (S / kseg segments of kseg states).  Collective.
+// Backward of syndrome b over its four cosets.  The top-down sweep runs here
+// (the rows before H->shared_rows once, as in the forward pass, then each
+// coset from the state after them), storing the MPS before every row; its log
+// Z values give the coset weights grad_logp[b] * P(l|s).  Then each coset
+// with a non-zero weight sweeps a second MPS up from the bottom with
+// transposed row MPOs and contracts the environments of every row against
+// the stored top state: nothing is recomputed.  Scratch layout (Real
+// elements): top regions | bottom regions | stored states (the shared rows
+// once, then nstep - S per coset; mps_elems each) | environments | three
+// temporaries.  write_fwd: also write log Z and log P(s) of the item.
+// Collective.
 template <typename Real, typename Fac, int GM>
 __device__ void adjoint_syndrome(const JobDev& job, int64_t b, uint8_t* smem, const LdsLayout& lay, Real* scr,
-                                 int kseg, double* part) {
+                                 int write_fwd, double* part) {
   const uint8_t* plan = job.plan;
   const PlanHeader* H = reinterpret_cast<const PlanHeader*>(plan);
   const int n = H->n, m = H->m, nsite = H->nsite, nstep = H->nstep;
-  const int S = H->shared_rows;
+  const int S = H->shared_rows < nstep ? H->shared_rows : nstep;
   const SiteStep* steps = reinterpret_cast<const SiteStep*>(plan + H->steps_ofs);
   const SiteStep* bsteps = reinterpret_cast<const SiteStep*>(plan + H->bu_steps_ofs);
   const uint8_t* codes = plan + H->codes_ofs;
@@ -214,40 +262,31 @@ __device__ void adjoint_syndrome(const JobDev& job, int64_t b, uint8_t* smem, co
   const int16_t* fin = reinterpret_cast<const int16_t*>(plan + H->final_ofs);
   __shared__ int s_flags[2];
   __shared__ int s_label;
+  __shared__ int s_lab[4];
+  __shared__ double s_lz[4];
   __shared__ double s_weight[4];
   Work<Real, Fac> w = carve<Real, Fac>(smem, lay, s_flags);
   const ItemCheck ck = check_item(job, b, n, m);
-  if (!ck.valid) return;  // no contribution; the status word says why
+  if (!ck.valid) {  // no contribution; the status word says why
+    if (write_fwd && threadIdx.x < 4) job.logz[b * 4 + threadIdx.x] = -INFINITY;
+    if (write_fwd && threadIdx.x == 0) const_cast<double*>(job.logp)[b] = -INFINITY;
+    __syncthreads();
+    return;
+  }
   const int model = ck.model;
   const double* rates = job.rates + (int64_t)model * n * 3;
   const uint8_t* syn = job.syn + b * m;
-  int first = -1;
-  for (int mlog = 0; mlog < 4; ++mlog) {
-    const int label = prep_reference(H, checks, syn, mlog, w.syn, w.fbits, &s_label);
-    if (threadIdx.x == 0) {
-      const double lz = job.logz[b * 4 + label], lp = job.logp[b], gp = job.gradp[b];
-      s_weight[mlog] = (lz > -INFINITY && lp > -INFINITY && gp != 0.0) ? gp * exp(lz - lp) : 0.0;
-    }
-    __syncthreads();
-    if (first < 0 && s_weight[mlog] != 0.0) first = mlog;
-  }
-  if (first < 0) return;
-
   const int64_t se = H->scratch_elems, me = H->mps_elems;
-  const int ncp = (nstep + kseg - 1) / kseg;
   Real* top = scr;
   Real* bot = scr + se;
-  Real* cps = scr + 2 * se;
-  Real* seg = cps + (int64_t)ncp * me;
-  Real* env = seg + (int64_t)kseg * me;
+  Real* states = scr + 2 * se;
+  Real* env = states + (int64_t)(S + 4 * (nstep - S)) * me;
   Real* P1 = env + H->env_elems;
   Real* P2 = P1 + H->tmp_elems;
   Real* P3 = P2 + H->tmp_elems;
-  Real* snap = P3 + H->tmp_elems;
-  Real* shseg = snap + me;
-  const int nshc = S / kseg;  // segments entirely within the shared rows
-  unsigned shdone = 0;        // bit c: shared segment c recomputed
-  double* pm = part + (int64_t)model * n * 3;
+  auto state_of = [&](int mlog, int u) -> Real* {
+    return states + (u < S ? (int64_t)u : (int64_t)S + (int64_t)mlog * (nstep - S) + (u - S)) * me;
+  };
   auto in_dims = [&](const SiteStep* row) {
     return [row](int J, int& Dl, int& q, int& Dr) {
       Dl = row[J].Dl_old;
@@ -255,69 +294,75 @@ __device__ void adjoint_syndrome(const JobDev& job, int64_t b, uint8_t* smem, co
       Dr = row[J].Dr_old;
     };
   };
-  // --- shared rows: top-down once, with their checkpoints ------------------
-  // (the reference error of any coset agrees on these rows)
-  prep_reference(H, checks, syn, first, w.syn, w.fbits, &s_label);
+  // --- top-down: the shared rows once (the reference error of any coset
+  // agrees on them), then each coset, storing the state before every row ---
+  prep_reference(H, checks, syn, 0, w.syn, w.fbits, &s_label);
   mps_ones(top, region, plan + H->init_qi_ofs, nsite);
-  double logscale = 0.0;
-  for (int u = 0; u < S; ++u) {
+  double base = 0.0;
+  bool alive = true;
+  for (int u = 0; u < S && alive; ++u) {
     const SiteStep* row = steps + (int64_t)u * nsite;
-    if (u % kseg == 0) mps_pack(top, region, nsite, in_dims(row), cps + (int64_t)(u / kseg) * me, false, top);
-    if (!row_step_outlined<Real, Fac, GM>(row, nsite, codes, rates, top, region, w, logscale)) return;
+    mps_pack(top, region, nsite, in_dims(row), state_of(0, u), false, top);
+    alive = row_step_outlined<Real, Fac, GM>(row, nsite, codes, rates, top, region, w, base);
   }
-  if (S > 0) mps_pack(top, region, nsite, in_dims(steps + (int64_t)S * nsite), snap, false, top);
-  const double logscale_s = logscale;
-
-  for (int mlog = first; mlog < 4; ++mlog) {
+  int dead = 0;  // thread 0: cosets with Z = 0
+  for (int mlog = 0; mlog < 4; ++mlog) {
+    const int label = prep_reference(H, checks, syn, mlog, w.syn, w.fbits, &s_label);
+    double logscale = base;
+    bool ok = alive;
+    if (ok && mlog > 0 && S < nstep)  // restart from the state after the shared rows
+      mps_pack(top, region, nsite, in_dims(steps + (int64_t)S * nsite), state_of(0, S), true, top);
+    for (int u = S; u < nstep && ok; ++u) {
+      const SiteStep* row = steps + (int64_t)u * nsite;
+      mps_pack(top, region, nsite, in_dims(row), state_of(mlog, u), false, top);
+      ok = row_step_outlined<Real, Fac, GM>(row, nsite, codes, rates, top, region, w, logscale);
+    }
+    const double lz = finish_logz(ok ? logscale + mps_close<Real, Fac>(top, region, fin, nsite, w.sig) : -INFINITY);
+    if (threadIdx.x == 0) {
+      s_lz[mlog] = lz;
+      s_lab[mlog] = label;
+      dead += lz == -INFINITY;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double mx = -INFINITY;
+    for (int k = 0; k < 4; ++k) mx = s_lz[k] > mx ? s_lz[k] : mx;
+    double lp = -INFINITY;
+    if (mx > -INFINITY) {
+      double sum = 0.0;
+      for (int k = 0; k < 4; ++k) sum += exp(s_lz[k] - mx);
+      lp = mx + log(sum);
+    }
+    const double gp = job.gradp[b];
+    for (int k = 0; k < 4; ++k)
+      s_weight[k] = (s_lz[k] > -INFINITY && lp > -INFINITY && gp != 0.0) ? gp * exp(s_lz[k] - lp) : 0.0;
+    if (write_fwd) {
+      for (int k = 0; k < 4; ++k) job.logz[b * 4 + s_lab[k]] = s_lz[k];
+      const_cast<double*>(job.logp)[b] = lp;
+      report_dead(dead, ck, job);
+    }
+  }
+  __syncthreads();
+  double* pm = part + (int64_t)model * n * 3;
+  // --- bottom-up per coset, against the stored top states ------------------
+  for (int mlog = 0; mlog < 4; ++mlog) {
     const double weight = s_weight[mlog];
     if (weight == 0.0) continue;
     prep_reference(H, checks, syn, mlog, w.syn, w.fbits, &s_label);
-    // --- the coset's own rows: top-down with checkpoints every kseg rows ----
-    if (S > 0) mps_pack(top, region, nsite, in_dims(steps + (int64_t)S * nsite), snap, true, top);
-    else mps_ones(top, region, plan + H->init_qi_ofs, nsite);
-    logscale = logscale_s;
-    bool alive = true;
-    for (int u = S; u < nstep && alive; ++u) {
-      const SiteStep* row = steps + (int64_t)u * nsite;
-      if (u % kseg == 0) mps_pack(top, region, nsite, in_dims(row), cps + (int64_t)(u / kseg) * me, false, top);
-      alive = row_step_outlined<Real, Fac, GM>(row, nsite, codes, rates, top, region, w, logscale);
-    }
-    if (!alive) continue;
-    // --- bottom-up, recomputing each segment of top states -----------------
     for (int J = 0; J < nsite; ++J)  // all-ones over the final frontier
       for (int e = threadIdx.x; e < fin[3 * J + 1]; e += NT) bot[region[J] + e] = Real(1);
     __syncthreads();
-    int cur = -1;
     double bscale = 0.0;
-    Real* sbase = seg;
-    for (int u = nstep - 1; u >= 0 && alive; --u) {
-      const int c = u / kseg;
-      if (c != cur) {
-        const bool shared = c < nshc;
-        sbase = shared ? shseg + (int64_t)c * kseg * me : seg;
-        if (!(shared && (shdone >> c & 1u))) {
-          const int t0 = c * kseg, t1 = (t0 + kseg < nstep ? t0 + kseg : nstep);
-          mps_pack(top, region, nsite, in_dims(steps + (int64_t)t0 * nsite), cps + (int64_t)c * me, true, top);
-          mps_pack(top, region, nsite, in_dims(steps + (int64_t)t0 * nsite), sbase, false, top);
-          for (int t = t0; t + 1 < t1 && alive; ++t) {
-            alive = row_step_outlined<Real, Fac, GM>(steps + (int64_t)t * nsite, nsite, codes, rates, top, region, w,
-                                                     logscale);
-            if (alive)
-              mps_pack(top, region, nsite, in_dims(steps + (int64_t)(t + 1) * nsite),
-                       sbase + (int64_t)(t + 1 - t0) * me, false, top);
-          }
-          if (shared && alive) shdone |= 1u << c;
-        }
-        cur = c;
-      }
-      if (!alive) break;
+    bool ok = true;
+    for (int u = nstep - 1; u >= 0 && ok; --u) {
       const SiteStep* frow = steps + (int64_t)u * nsite;
       const SiteStep* brow = bsteps + (int64_t)(nstep - 1 - u) * nsite;
-      if (!row_gradient<Real>(frow, brow, nsite, codes, rates, w.fbits, sbase + (int64_t)(u - c * kseg) * me, bot,
-                              region, env, P1, P2, P3, w.Wv, weight, pm) &&
+      if (!row_gradient<Real>(frow, brow, nsite, codes, rates, w.fbits, state_of(mlog, u), bot, region, env, P1, P2,
+                              P3, w.Wv, weight, pm, smem, lay, H->tmp_elems) &&
           ck.positive && threadIdx.x == 0 && job.status)
         atomicOr(job.status, ST_NUMERIC);
-      if (u > 0) alive = row_step_outlined<Real, Fac, GM>(brow, nsite, codes, rates, bot, region, w, bscale);
+      if (u > 0) ok = row_step_outlined<Real, Fac, GM>(brow, nsite, codes, rates, bot, region, w, bscale);
     }
   }
 }

@@ -343,6 +343,7 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
       const SiteStep& Bv = bu[(size_t)(nstep - 1 - u) * nsite + std::min(J, nsite - 1)];
       int dt = J == nsite ? 1 : T.Dl_old, db = J == nsite ? 1 : Bv.Dl_old, a = J == nsite ? 1 : T.A;
       env += (int64_t)dt * a * db;
+      h.max_envb = std::max(h.max_envb, dt * a * db);
     }
     env_max = std::max(env_max, env);
   }
@@ -451,6 +452,8 @@ void merge_maxima(PlanHeader* a, const PlanHeader& h) {
   a->max_m = std::max(a->max_m, h.max_m);
   a->max_rows = std::max(a->max_rows, h.max_rows);
   a->max_bond = std::max(a->max_bond, h.max_bond);
+  a->max_envb = std::max(a->max_envb, h.max_envb);
+  a->tmp_elems = std::max(a->tmp_elems, h.tmp_elems);
   a->n = std::max(a->n, h.n);
   a->m = std::max(a->m, h.m);
 }

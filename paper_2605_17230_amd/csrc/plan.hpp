@@ -90,6 +90,8 @@ struct PlanHeader {  // device-visible, followed by the tables at the offsets be
   int32_t max_V;    // (kr + 1) * kr                  right rotations
   int32_t max_Q;    // k * qo * kr                    staged orthonormal site
   int32_t max_kr, max_n, max_m, max_rows, max_bond;
+  int32_t max_envb;     // one bond of a row environment (adjoint): top bond * MPO bond * bottom bond
+  int32_t pad_h;
   int32_t shared_rows;  // rows 0..shared_rows-1 touch no qubit of the logical representatives:
                         // their MPOs, hence the MPS after them, are the same for all four cosets
   double flops_fwd;     // counted flops of one coset's contraction (see count in plan.cpp)
@@ -122,6 +124,11 @@ struct LdsLayout {
   int32_t W;                          // MPO values of the current site (<= 64, storage type)
   int32_t red, perm, rank, fbits, syn;  // FP64 reduction scratch, kept columns, column sets, reference-error bits, syndrome
   int32_t nrm;                         // FP64 squared column norms of the truncation SVD
+  // adjoint row environments (between row steps, over the storage of the two
+  // sweep phases; -1 = kept in the work-group's global scratch instead):
+  // three contraction temporaries, the top and bottom site, two bonds of
+  // environment
+  int32_t gP, gA, gF, gE, gR;
   int32_t bytes;
 };
 
@@ -160,6 +167,23 @@ inline LdsLayout lds_layout(const PlanHeader& h, int rb, int fb, bool aj_global 
   o.tau = p; p += pad64b((int64_t)nh * fb);
   o.diag = p; p += pad64b((int64_t)nh * fb);
   o.v = p; p += pad64b((int64_t)2 * nv * fb);
+  {
+    // the adjoint's environment contractions run between row steps: their
+    // buffers reuse the storage of the two sweep phases [0, phase_end)
+    const int32_t phase_end = rl_end > lr_end ? rl_end : lr_end;
+    const int32_t tP = pad64b((int64_t)h.tmp_elems * rb), tS = pad64b((int64_t)h.max_Aj * rb),
+                  tE = pad64b((int64_t)h.max_envb * rb);
+    o.gP = o.gA = o.gF = o.gE = o.gR = -1;
+    if (3 * tP + 2 * tS + 2 * tE <= phase_end) {
+      o.gP = 0;
+      o.gA = 3 * tP;
+      o.gF = o.gA + tS;
+      o.gE = o.gF + tS;
+      o.gR = o.gE + tE;
+    } else if (3 * tP <= phase_end) {
+      o.gP = 0;
+    }
+  }
   o.W = p; p += pad64b(64 * rb);
   o.red = p; p += 64 * 8;
   o.nrm = p; p += pad64b((int64_t)(h.max_kr > h.max_bond ? h.max_kr : h.max_bond) * 8);

@@ -42,6 +42,9 @@ namespace tnmld_small {
 int small_wgs_per_cu(int precision, int lds_bytes);
 int launch_fwd_small(int precision, const void* jt, unsigned long long* counter, char* scratch, int64_t stride,
                      int64_t snap_ofs, const void* lay, int lds_bytes, int nwg, hipStream_t st);
+int small_bwd_wgs_per_cu(int precision, int lds_bytes);
+int launch_bwd_small(int precision, const void* jt, char* scratch, int64_t stride, const void* lay, int lds_bytes,
+                     int write_fwd, double* partials, int64_t pstride, int nwg, hipStream_t st);
 }  // namespace tnmld_small
 
 namespace tnmld {
@@ -74,7 +77,7 @@ __global__ __launch_bounds__(NT) void fwd_kernel(JobTable jt, unsigned long long
 // and accumulates into its own FP64 partial gradient.
 template <typename Real, typename Fac, int GM>
 __global__ __launch_bounds__(NT) void bwd_kernel(JobTable jt, char* scratch, int64_t scratch_stride, LdsLayout lay,
-                                                  int kseg, double* partials, int64_t part_stride) {
+                                                  int write_fwd, double* partials, int64_t part_stride) {
   extern __shared__ __align__(16) uint8_t smem[];
   Real* scr = reinterpret_cast<Real*>(scratch + (int64_t)blockIdx.x * scratch_stride);
   double* mypart = partials + (int64_t)blockIdx.x * part_stride;
@@ -82,7 +85,7 @@ __global__ __launch_bounds__(NT) void bwd_kernel(JobTable jt, char* scratch, int
     int jb = 0;
     while (jb + 1 < jt.n && jt.j[jb + 1].item_begin <= item) ++jb;
     const JobDev& job = jt.j[jb];
-    adjoint_syndrome<Real, Fac, GM>(job, item - job.item_begin, smem, lay, scr, kseg, mypart + job.part_ofs);
+    adjoint_syndrome<Real, Fac, GM>(job, item - job.item_begin, smem, lay, scr, write_fwd, mypart + job.part_ofs);
     __syncthreads();
   }
 }
@@ -616,9 +619,11 @@ struct BwdLayout {
   JobTable jt{};
   int seg_of_job[TN_MAX_SEGMENTS] = {};
   PlanHeader merged{};
-  int nwg = 0, kseg = 1;
+  int nwg = 0;
+  bool small = false;      // 256-thread build (two or more work-groups per CU)
+  bool aj_global = false;  // small build without the LDS copy of the input site
   int64_t scratch_stride = 0, part_stride = 0;
-  size_t fwd_bytes = 0, total = 0;
+  size_t hdr_bytes = 0, total = 0;
 };
 
 int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
@@ -629,16 +634,11 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
   int rc = validate(segs, nseg);
   if (rc) return rc;
   if ((rc = device_info(&di))) return rc;
-  {
-    // the forward pass that supplies log Z runs with its own launch split
-    std::vector<Launch> fl;
-    if ((rc = plan_launches(segs, nseg, std::min(di.lds_max, kLdsLimit), &fl, &fwd, &nwgf, true))) return rc;
-    bl->fwd_bytes = align_up(fwd);
-  }
+  bl->hdr_bytes = kAlign;  // counters and the status word
   if ((rc = plan_launches(segs, nseg, std::min(di.lds_max, kLdsLimit), &launches, &fwd, &nwgf, false))) return rc;
   if (launches.size() > 1) return fail(TN_EUNSUPPORTED, "backward segments must share one precision");
   if (launches.empty()) {
-    bl->total = bl->fwd_bytes;
+    bl->total = bl->hdr_bytes;
     return TN_OK;
   }
   const Launch& L = launches[0];
@@ -660,7 +660,6 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return segs[a].d > segs[b].d; });
   int ji = 0;
   int64_t part = 0, per_item = 0;
-  int nstep_max = 1;
   for (int oi : order) {
     if (segs[oi].count == 0) continue;
     bl->seg_of_job[ji] = oi;
@@ -675,36 +674,39 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
         if (kv.second->dev == j.plan) H = &kv.second->plan.h;
     }
     if (!H) return fail(TN_EDEVICE, "internal: plan not cached");
-    const int ks = (int)std::ceil(std::sqrt((double)H->nstep));
-    const int ncp = (H->nstep + ks - 1) / ks;
-    nstep_max = std::max(nstep_max, H->nstep);
-    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems + (int64_t)(ncp + ks + 1 + H->shared_rows) *
-                                               H->mps_elems + H->env_elems + 3 * H->tmp_elems);
-    ++ji;
-  }
-  bl->kseg = (int)std::ceil(std::sqrt((double)nstep_max));
-  // recompute the per-item scratch with the common segment length
-  per_item = 0;
-  for (int i = 0; i < ji; ++i) {
-    const PlanHeader* H = nullptr;
-    {
-      std::lock_guard<std::mutex> lk(g_mu);
-      for (auto& kv : g_plans)
-        if (kv.second->dev == bl->jt.j[i].plan) H = &kv.second->plan.h;
-    }
-    const int ncp = (H->nstep + bl->kseg - 1) / bl->kseg;
-    // checkpoints, segment states, the snapshot after the shared rows and the
-    // kept states of the segments within them
-    const int nshc = H->shared_rows / bl->kseg;
-    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems +
-                                               (int64_t)(ncp + bl->kseg + 1 + nshc * bl->kseg) * H->mps_elems +
+    // work and bottom regions, the stored top states (the shared rows once,
+    // the rest per coset), environments and three temporaries
+    const int S = std::min(H->shared_rows, H->nstep);
+    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems + (int64_t)(S + 4 * (H->nstep - S)) * H->mps_elems +
                                                H->env_elems + 3 * H->tmp_elems);
+    ++ji;
   }
   const int lb = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision)).bytes;
   bl->nwg = std::max(1, wgs_for(lb, bwd_kernel_of(L.precision))) * di.cus;
+  {
+    // the 256-thread build when its plan fits (as for the forward pass) and
+    // at least two of its work-groups share a CU
+    const int rpg = fac_bytes(L.precision) == 4 ? 4 : 2;
+    const PlanHeader& h = L.merged;
+    if (h.max_m <= rpg * (kSmallNT / 16) && h.max_n <= 256 && h.max_bond <= kSmallNT) {
+      const int limit = kLdsPerCU / 2 - 256;
+      bool ajg = false;
+      int sb = lb;
+      if (sb > limit) {
+        sb = lds_layout(h, real_bytes(L.precision), fac_bytes(L.precision), true).bytes;
+        ajg = true;
+      }
+      const int ws = sb <= limit ? tnmld_small::small_bwd_wgs_per_cu(L.precision, sb) : 0;
+      if (ws >= 2) {
+        bl->small = true;
+        bl->aj_global = ajg;
+        bl->nwg = std::min(ws, kLdsPerCU / (sb + 256)) * di.cus;
+      }
+    }
+  }
   bl->scratch_stride = (int64_t)align_up((size_t)per_item * real_bytes(L.precision));
   bl->part_stride = (part + 31) / 32 * 32;
-  bl->total = bl->fwd_bytes + align_up((size_t)bl->nwg * bl->part_stride * sizeof(double)) +
+  bl->total = bl->hdr_bytes + align_up((size_t)bl->nwg * bl->part_stride * sizeof(double)) +
               (size_t)bl->nwg * bl->scratch_stride;
   return TN_OK;
 }
@@ -787,31 +789,32 @@ int tn_coset_loglik_backward(const tn_segment* segs, int32_t nseg, const double*
   }
   if (!workspace || ws_bytes < bl.total) return fail(TN_EINVAL, "workspace too small: need " + std::to_string(bl.total));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  // forward pass: log Z and log P(s) (the coset weights of the backward)
-  if (!forward_done && (rc = tn_coset_loglik(segs, nseg, workspace, ws_bytes, stream))) return rc;
-  char* base = reinterpret_cast<char*>(workspace) + bl.fwd_bytes;
-  double* partials = reinterpret_cast<double*>(base);
-  char* scratch = base + align_up((size_t)bl.nwg * bl.part_stride * sizeof(double));
   unsigned* status = status_word(workspace);
-  if (forward_done) zero_status<<<1, 64, 0, st>>>(status);  // else the forward call cleared it
+  zero_status<<<1, 64, 0, st>>>(status);
+  if (bl.jt.n == 0) return TN_OK;
+  char* base = reinterpret_cast<char*>(workspace) + bl.hdr_bytes;
+  double* partials = reinterpret_cast<double*>(base);
+  char* scratch_base = base + align_up((size_t)bl.nwg * bl.part_stride * sizeof(double));
   fill_zero_f64<<<256, 256, 0, st>>>(partials, (int64_t)bl.nwg * bl.part_stride);
   JobTable jt = bl.jt;
   for (int i = 0; i < jt.n; ++i) {
     jt.j[i].gradp = grad_logp[bl.seg_of_job[i]];
     jt.j[i].status = status;
   }
-  LdsLayout lay = lds_layout(bl.merged, real_bytes(bl.precision), fac_bytes(bl.precision));
-  const void* kern = nullptr;
-  if (bl.precision == TN_FP64) kern = reinterpret_cast<const void*>(bwd_kernel<double, double, GEMM_VALU>);
-  else if (bl.precision == TN_FP32) kern = reinterpret_cast<const void*>(bwd_kernel<float, double, GEMM_VALU>);
-  else if (bl.precision == TN_BF16) kern = reinterpret_cast<const void*>(bwd_kernel<float, float, BF16_GEMM_MODE>);
-  else kern = reinterpret_cast<const void*>(bwd_kernel<float, float, GEMM_VALU>);
-  if ((rc = ensure_lds_attr(kern, lay.bytes))) return rc;
-  int kseg = bl.kseg;
+  LdsLayout lay = lds_layout(bl.merged, real_bytes(bl.precision), fac_bytes(bl.precision), bl.aj_global);
+  int write_fwd = forward_done ? 0 : 1;
   int64_t sstride = bl.scratch_stride, pstride = bl.part_stride;
-  void* args[] = {&jt, &scratch, &sstride, &lay, &kseg, &partials, &pstride};
-  if (hipLaunchKernel(kern, dim3(bl.nwg), dim3(NT), args, lay.bytes, st) != hipSuccess)
-    return fail(TN_EDEVICE, "backward launch failed");
+  if (bl.small) {
+    if (tnmld_small::launch_bwd_small(bl.precision, &jt, scratch_base, sstride, &lay, lay.bytes, write_fwd, partials,
+                                      pstride, bl.nwg, st) != 0)
+      return fail(TN_EDEVICE, "backward launch failed");
+  } else {
+    const void* kern = bwd_kernel_of(bl.precision);
+    if ((rc = ensure_lds_attr(kern, lay.bytes))) return rc;
+    void* args[] = {&jt, &scratch_base, &sstride, &lay, &write_fwd, &partials, &pstride};
+    if (hipLaunchKernel(kern, dim3(bl.nwg), dim3(NT), args, lay.bytes, st) != hipSuccess)
+      return fail(TN_EDEVICE, "backward launch failed");
+  }
   for (int i = 0; i < jt.n; ++i) {
     const tn_segment& sg = segs[bl.seg_of_job[i]];
     const int64_t len = (int64_t)sg.n_models * sg.d * sg.d * 3;

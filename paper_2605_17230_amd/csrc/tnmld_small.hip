@@ -11,7 +11,7 @@
 
 #define TNMLD_NT 256
 #define tnmld tnmld_small
-#include "contract.hpp"
+#include "adjoint.hpp"
 
 #ifndef BF16_GEMM_MODE
 #define BF16_GEMM_MODE GEMM_BF16X3
@@ -40,6 +40,23 @@ __global__ __launch_bounds__(NT) void fwd_kernel_small(JobTable jt, unsigned lon
   }
 }
 
+// Backward on 256-thread work-groups (see bwd_kernel in tnmld.hip).
+template <typename Real, typename Fac, int GM>
+__global__ __launch_bounds__(NT) void bwd_kernel_small(JobTable jt, char* scratch, int64_t scratch_stride,
+                                                        LdsLayout lay, int write_fwd, double* partials,
+                                                        int64_t part_stride) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  Real* scr = reinterpret_cast<Real*>(scratch + (int64_t)blockIdx.x * scratch_stride);
+  double* mypart = partials + (int64_t)blockIdx.x * part_stride;
+  for (int64_t item = blockIdx.x; item < jt.nitems; item += gridDim.x) {
+    int jb = 0;
+    while (jb + 1 < jt.n && jt.j[jb + 1].item_begin <= item) ++jb;
+    const JobDev& job = jt.j[jb];
+    adjoint_syndrome<Real, Fac, GM>(job, item - job.item_begin, smem, lay, scr, write_fwd, mypart + job.part_ofs);
+    __syncthreads();
+  }
+}
+
 __global__ void zero_one(unsigned long long* c) {
   if (threadIdx.x == 0) *c = 0ull;
 }
@@ -50,6 +67,13 @@ const void* kernel_of(int precision) {
   if (precision == TN_FP32) return reinterpret_cast<const void*>(fwd_kernel_small<float, double, GEMM_VALU>);
   if (precision == TN_BF16) return reinterpret_cast<const void*>(fwd_kernel_small<float, float, BF16_GEMM_MODE>);
   return reinterpret_cast<const void*>(fwd_kernel_small<float, float, GEMM_VALU>);
+}
+
+const void* bwd_kernel_of(int precision) {
+  if (precision == TN_FP64) return reinterpret_cast<const void*>(bwd_kernel_small<double, double, GEMM_VALU>);
+  if (precision == TN_FP32) return reinterpret_cast<const void*>(bwd_kernel_small<float, double, GEMM_VALU>);
+  if (precision == TN_BF16) return reinterpret_cast<const void*>(bwd_kernel_small<float, float, BF16_GEMM_MODE>);
+  return reinterpret_cast<const void*>(bwd_kernel_small<float, float, GEMM_VALU>);
 }
 
 int raise_lds(const void* kern, int bytes) {
@@ -94,6 +118,28 @@ int launch_fwd_small(int precision, const void* jt, unsigned long long* counter,
   JobTable t = *reinterpret_cast<const JobTable*>(jt);
   LdsLayout l = *reinterpret_cast<const LdsLayout*>(lay);
   void* args[] = {&t, &counter, &scratch, &stride, &snap_ofs, &l};
+  if (hipLaunchKernel(kern, dim3(nwg), dim3(NT), args, (size_t)lds_bytes, st) != hipSuccess) return -1;
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Work-groups of the small backward kernel that one CU holds (0 if unknown).
+int small_bwd_wgs_per_cu(int precision, int lds_bytes) {
+  const void* kern = bwd_kernel_of(precision);
+  int nb = 0;
+  if (raise_lds(kern, lds_bytes) != 0 ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, (size_t)lds_bytes) != hipSuccess)
+    nb = 0;
+  return nb;
+}
+
+// Enqueue the small backward kernel (jt, lay: the caller's JobTable / LdsLayout).
+int launch_bwd_small(int precision, const void* jt, char* scratch, int64_t stride, const void* lay, int lds_bytes,
+                     int write_fwd, double* partials, int64_t pstride, int nwg, hipStream_t st) {
+  const void* kern = bwd_kernel_of(precision);
+  if (raise_lds(kern, lds_bytes) != 0) return -1;
+  JobTable t = *reinterpret_cast<const JobTable*>(jt);
+  LdsLayout l = *reinterpret_cast<const LdsLayout*>(lay);
+  void* args[] = {&t, &scratch, &stride, &l, &write_fwd, &partials, &pstride};
   if (hipLaunchKernel(kern, dim3(nwg), dim3(NT), args, (size_t)lds_bytes, st) != hipSuccess) return -1;
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -62,16 +62,15 @@ int gradient(int d, int chi, int group, const double* rates, const uint8_t* syn,
   if (!build_plan(d, chi, group, &p).empty()) return -1;
   const PlanHeader& H = p.h;
   const LdsLayout lay = lds_layout(H, sizeof(Real), sizeof(Fac));
-  const int kseg = (int)std::ceil(std::sqrt((double)H.nstep));
-  const int ncp = (H.nstep + kseg - 1) / kseg;
-  const int64_t elems = 2 * H.scratch_elems + (int64_t)(ncp + kseg + 1 + H.shared_rows / kseg * kseg) * H.mps_elems +
-                       H.env_elems + 3 * H.tmp_elems;
+  const int S = H.shared_rows < H.nstep ? H.shared_rows : H.nstep;
+  const int64_t elems = 2 * H.scratch_elems + (int64_t)(S + 4 * (H.nstep - S)) * H.mps_elems + H.env_elems +
+                        3 * H.tmp_elems;
   std::vector<double> smem(lay.bytes / 8 + 16), scr(elems * sizeof(Real) / 8 + 16);
   JobDev job{p.blob.data(), rates, nullptr, syn, const_cast<double*>(logz), logp, gradp, count, 0, 0, 1, 0, nullptr};
   Barriers bars;
   for (int b = 0; b < count; ++b)
     run_block([&](int) {
-      adjoint_syndrome<Real, Fac, GEMM_VALU>(job, b, (uint8_t*)smem.data(), lay, (Real*)scr.data(), kseg, out);
+      adjoint_syndrome<Real, Fac, GEMM_VALU>(job, b, (uint8_t*)smem.data(), lay, (Real*)scr.data(), 0, out);
     });
   return 0;
 }

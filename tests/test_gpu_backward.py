@@ -247,8 +247,8 @@ def test_c5_gradient_full_batch():
 
 
 def test_backward_reuses_forward_outputs():
-    """Passing the outputs of an earlier decode skips the forward pass and
-    gives the same gradient, bit for bit."""
+    """Passing the outputs of an earlier decode (forward_done) gives the same
+    gradient, bit for bit, and leaves those outputs as they were."""
     tn = _tn()
     d, chi = 7, 12
     rates = synth.biased(d, 0.1, 10.0)
@@ -257,5 +257,7 @@ def test_backward_reuses_forward_outputs():
     gw = torch.from_numpy(np.random.default_rng(3).normal(size=64)).to(DEV)
     _, g_full = tn.coset_loglik_backward([seg], [gw])
     outs = tn.decode_segments([seg])
+    before = outs[0].logz.clone()
     _, g_reuse = tn.coset_loglik_backward([seg], [gw], outputs=outs)
     assert torch.equal(g_full[0], g_reuse[0])
+    assert torch.equal(outs[0].logz, before)

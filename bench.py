@@ -10,12 +10,16 @@ timed once beside it, and both are compared with the FP64 form on a sample.
 Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--precision bf16|fp32plain|fp32|fp64]
-                  [--compare fp32plain] [--workload c3|c4|c5] [--cpu-seconds S] [--no-cpu]
+                  [--compare fp32plain] [--workload c2|c3|c4|c5|fit|study|planar]
+                  [--cpu-seconds S] [--cpu-min N] [--no-cpu]
 
---workload c4 decodes the mixed batch (distances 5..15) in one launch;
---workload c5 times the adjoint (forward + backward) on the gradient workload
-(d = 11, per-qubit log-uniform rates, 8,192 syndromes, chi = 24, FP32 unless
---precision says otherwise).
+--workload c2 decodes the d = 9 p-sweep (five noise levels, 65,536 syndromes
+each) in one call in the plain FP32 form and reports the logical error rate
+per p; c4 decodes the mixed batch (distances 5..15) in one call; c5 times the
+adjoint (forward + backward) on the gradient workload (d = 11, per-qubit
+log-uniform rates, 8,192 syndromes, chi = 24, FP32 unless --precision says
+otherwise); fit runs the noise-model fit; study the logical-error and chi
+sweeps; planar the exact bit-flip solver at d = 17.
 """
 import argparse
 import json
@@ -40,19 +44,26 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="bf16")
+    ap.add_argument("--precision", default=None,
+                    help="form timed (default: bf16; fp32plain for c2, as that workload names; fp32 for c5 and fit)")
     ap.add_argument("--compare", default="fp32plain", help="second form timed once ('' to skip)")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5", "fit", "study", "planar"])
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5", "fit", "study", "planar"])
     ap.add_argument("--study-count", type=int, default=4096, help="syndromes per (d, p) point of the study")
     ap.add_argument("--fit-steps", type=int, default=60, help="Adam steps of the fit workload")
     ap.add_argument("--fit-batch", type=int, default=1024, help="syndromes per step of the fit workload")
+    ap.add_argument("--fit-ns", default="1024,2048,4096,8192", help="data sizes N of the fit workload")
     ap.add_argument("--count", type=int, default=COUNT)
-    ap.add_argument("--fp64-sample", type=int, default=512, help="syndromes decoded in FP64 for the error report")
+    ap.add_argument("--fp64-sample", type=int, default=16384,
+                    help="syndromes decoded in FP64 at the same chi for the precision-error report (0: none)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-min", type=int, default=256, help="fewest syndromes the oracle baseline times")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (reference kernel for HBM byte counters)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.precision is None:
+        a.precision = {"c2": "fp32plain", "c5": "fp32", "fit": "fp32"}.get(a.workload, "bf16")
+    return a
 
 
 def copy_calibration():
@@ -66,16 +77,36 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}), flush=True)
 
 
-def cpu_baseline(d, rates, syn, target_s):
-    """FP64 oracle (exact transfer-matrix contraction) on a bounded prefix."""
+def environment():
+    """Hardware and software the line was measured on."""
+    import platform
+    import torch
+    cpu = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"gpu": torch.cuda.get_device_name(0), "rocm_hip": torch.version.hip, "torch": torch.__version__,
+            "cpu": cpu, "nproc": os.cpu_count(),
+            "omp_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
+
+
+def cpu_baseline(d, rates, syn, target_s, min_count=256):
+    """FP64 oracle (exact transfer-matrix contraction) on a bounded prefix of
+    at least min_count syndromes (more while under target_s seconds)."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    n = max(threads, 1)
+    n = max(threads, min(min_count, len(syn)))
     t0 = time.time()
     ref = oracle.transfer(d, rates, syn[:n], threads=threads)
     dt = time.time() - t0
     per = dt / n * threads  # seconds per syndrome per thread
     more = int(max(0, target_s - dt) / max(per, 1e-9) * threads) // threads * threads
+    more = min(more, len(syn) - n)
     if more > 0:
         t1 = time.time()
         ref2 = oracle.transfer(d, rates, syn[n:n + more], threads=threads)
@@ -167,37 +198,61 @@ def bench_adjoint(a, torch, tn, synth, dev, stream):
 def bench_fit(a, torch, tn, synth, dev):
     """Noise-model fitting on the gradient workload: Adam on the per-qubit log
     rates from a uniform start, one forward + backward per step on a random
-    mini-batch of the syndromes."""
+    mini-batch, with the first N of its syndromes for each N of --fit-ns.
+    Reports the rate error against the generating rates per N and the logical
+    error rate of decoding fresh syndromes of the same model with the true,
+    the refitted (largest N) and the starting prior."""
     s = synth.config_inputs("C5")[0]
     prec = a.precision if a.precision != "bf16" else "fp32"
     d, chi = s["d"], s["chi"]
-    syn = torch.from_numpy(s["syndromes"]).to(dev)
-    true = torch.from_numpy(np.log(s["rates"][0])).to(dev)
-    theta0 = torch.full_like(true, float(np.log(s["rates"][0].mean())))
-    print("bench: fit d=%d chi=%d %s, %d syndromes, %d steps of %d" % (d, chi, prec, len(syn), a.fit_steps,
-                                                                       a.fit_batch), file=sys.stderr, flush=True)
-    tn.fit_log_rates(syn, d, chi, theta0, steps=1, batch=a.fit_batch, precision=prec)  # warm-up
+    syn_all = torch.from_numpy(s["syndromes"]).to(dev)
+    true_rates = s["rates"][0]
+    true = torch.from_numpy(np.log(true_rates)).to(dev)
+    theta0 = torch.full_like(true, float(np.log(true_rates.mean())))
+    ns = [int(x) for x in a.fit_ns.split(",")]
+    print("bench: fit d=%d chi=%d %s, N in %s, %d steps" % (d, chi, prec, ns, a.fit_steps), file=sys.stderr,
+          flush=True)
+    tn.fit_log_rates(syn_all[:256], d, chi, theta0, steps=1, batch=256, precision=prec)  # warm-up
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    theta, hist = tn.fit_log_rates(syn, d, chi, theta0, steps=a.fit_steps, lr=0.05, batch=a.fit_batch,
-                                   precision=prec)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
 
-    def loss(th):
+    def loss(th, syn):
         with torch.no_grad():
             return float(-tn.log_posterior(th, syn, d, chi, prec)[0].mean())
 
+    per_n = {}
+    theta_last, rate = None, None
+    for n in ns:
+        syn = syn_all[:n]
+        batch = min(a.fit_batch, n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        theta, hist = tn.fit_log_rates(syn, d, chi, theta0, steps=a.fit_steps, lr=0.05, batch=batch, precision=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err = (theta - true).abs()
+        per_n[str(n)] = {"mean_abs_log_rate_error": float(err.mean()), "median_abs_log_rate_error": float(err.median()),
+                         "loss_end": loss(theta, syn), "loss_true_rates": loss(true, syn), "seconds": dt}
+        print("bench: fit N=%d done: mean |d ln p| %.3f" % (n, float(err.mean())), file=sys.stderr, flush=True)
+        theta_last, rate = theta, a.fit_steps * batch / dt
+    # logical error rate on fresh syndromes of the generating model
+    test = synth.sample(d, true_rates, 8192, 5002)
+    tsyn = torch.from_numpy(test["syndromes"]).to(dev)
+    ler = {}
+    for name, th in (("true_prior", true), ("refit_prior_N=%d" % ns[-1], theta_last), ("start_prior", theta0)):
+        _, _, cls = tn.decode(tsyn, th.exp(), d, chi, prec)
+        ler[name] = float((cls.cpu().numpy() != test["true_class"]).mean())
     out = {
         "metric": "syndromes/s through the noise fit (forward + adjoint + Adam step) at d=11 chi=24",
-        "value": a.fit_steps * a.fit_batch / dt, "unit": "syndromes/s", "n_gpus": 1, "steps": a.fit_steps,
-        "warmup": 1, "ms_per_step": dt / a.fit_steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
-        "config": {"workload": "fit of 363 log rates to %d syndromes of the d=11 gradient model, chi=24, "
-                               "mini-batch %d, Adam lr 0.05" % (len(syn), a.fit_batch), "precision": prec},
-        "loss": {"start": loss(theta0), "end": loss(theta), "true_rates": loss(true)},
-        "mean_abs_log_rate_error": {"start": float((theta0 - true).abs().mean()),
-                                    "end": float((theta - true).abs().mean())},
+        "value": rate, "unit": "syndromes/s", "n_gpus": 1, "steps": a.fit_steps,
+        "warmup": 1, "ms_per_step": per_n[str(ns[-1])]["seconds"] / a.fit_steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
+        "config": {"workload": "fit of 363 log rates to the first N syndromes of the d=11 gradient model, chi=24, "
+                               "mini-batch %d, Adam lr 0.05, %d steps" % (a.fit_batch, a.fit_steps),
+                   "precision": prec},
+        "start": {"mean_abs_log_rate_error": float((theta0 - true).abs().mean())},
+        "rate_error_vs_N": per_n,
+        "logical_error_rate_fresh_8192": ler,
+        "environment": environment(),
     }
     print(json.dumps(out), flush=True)
 
@@ -341,8 +396,12 @@ def main():
         rates = synth.depolarizing(D, P)
         smp = synth.sample(D, rates, a.count, SEED)
         segs_h = [dict(d=D, chi=CHI, syndromes=smp["syndromes"], rates=rates,
-                       model_index=np.zeros(a.count, np.int32))]
+                       model_index=np.zeros(a.count, np.int32), true_class=smp["true_class"])]
         workload = "rotated surface code d=17, depolarizing p=0.12, %d seeded syndromes, chi=32" % a.count
+    elif a.workload == "c2":
+        segs_h = synth.config_inputs("C2")
+        workload = ("p-sweep at d=9, chi=16: depolarizing p in {0.05, 0.08, 0.11, 0.14, 0.17}, 65,536 seeded "
+                    "syndromes per p, one call")
     else:
         segs_h = synth.config_inputs("C4")
         workload = ("mixed batch in one launch: d=5..15 with 32768..1024 syndromes, biased p=0.08, "
@@ -416,6 +475,10 @@ def main():
                        "achieved": mf, "peak": PEAK_MFMA_BF16_TFLOPS, "unit": "TFLOP/s",
                        "frac": mf / PEAK_MFMA_BF16_TFLOPS, "bf16_products_per_gemm_flop": 3}
     print("bench: timed %.1f ms per step" % ms_step, file=sys.stderr, flush=True)
+    out["environment"] = environment()
+    if a.workload == "c2":
+        out["logical_error_rate"] = {
+            "p=%.2f" % sg["p"]: float((o.cls.cpu().numpy() != sg["true_class"]).mean()) for sg, o in zip(segs_h, outs)}
     lz = [o.logz.cpu().numpy() for o in outs]
     cls = [o.cls.cpu().numpy() for o in outs]
     o2 = None
@@ -438,25 +501,33 @@ def main():
         print("bench: compare %s %.1f ms" % (a.compare, ms2), file=sys.stderr, flush=True)
     if a.fp64_sample > 0 and a.workload == "c3":
         ns = min(a.fp64_sample, n_syn)
-        o64 = tn.decode_segments(inputs("fp64", ns))[0]
+        with __import__("warnings").catch_warnings():
+            __import__("warnings").simplefilter("ignore")
+            o64 = tn.decode_segments(inputs("fp64", ns))[0]
         ref64 = o64.logz.cpu().numpy()
         c64 = o64.cls.cpu().numpy()
         err = {"syndromes": ns, "chi": CHI}
         forms = [(a.precision, lz[0][:ns], cls[0][:ns])]
         if o2 is not None:
             forms.append((a.compare, o2[0].logz.cpu().numpy()[:ns], o2[0].cls.cpu().numpy()[:ns]))
+        with np.errstate(invalid="ignore"):
+            post = ref64 - np.logaddexp.reduce(ref64, 1)[:, None]
         for name, z, c in forms:
-            fin = np.isfinite(ref64)
-            err[name] = {"max_abs_dlogz": float(np.max(np.abs(np.where(fin, z - ref64, 0.0)))),
+            fin = np.isfinite(ref64) & np.isfinite(z)
+            dz = np.abs(np.where(fin, z - ref64, 0.0))
+            err[name] = {"max_abs_dlogz": float(dz.max()),
+                         "max_abs_dlogz_posterior_ge_e-10": float(dz[post >= -10].max(initial=0)),
+                         "max_abs_dlogz_posterior_ge_e-20": float(dz[post >= -20].max(initial=0)),
+                         "unresolved_cosets": int((np.isfinite(ref64) & ~np.isfinite(z)).sum()),
                          "max_abs_dlogp": float(np.max(np.abs(np.logaddexp.reduce(z, 1)
                                                               - np.logaddexp.reduce(ref64, 1)))),
                          "class_agreement": float(np.mean(c == c64))}
         out["error_vs_fp64_same_chi"] = err
-        print("bench: fp64 sample done", file=sys.stderr, flush=True)
+        print("bench: fp64 comparison done", file=sys.stderr, flush=True)
     if not a.no_cpu and a.workload == "c3":
         import oracle
         s0 = segs_h[0]
-        ref, n, dt, threads = cpu_baseline(D, s0["rates"], s0["syndromes"], a.cpu_seconds)
+        ref, n, dt, threads = cpu_baseline(D, s0["rates"], s0["syndromes"], a.cpu_seconds, a.cpu_min)
         _, rcls = oracle.decide(ref)
         fin = np.isfinite(ref)
         out["cpu_baseline"] = {"value": n / dt, "unit": "syndromes/s", "cores": threads, "kind": "oracle",

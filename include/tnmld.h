@@ -180,6 +180,19 @@ int tn_plan_gemm_flops(int32_t d, int32_t chi, int32_t precision, double* out);
  * sets these from its cache.  Returns TN_OK or TN_EINVAL. */
 int tn_set_tuning(int32_t d, int32_t chi, int32_t precision, int32_t group, int32_t wg_per_cu);
 
+/* HOST helper: tn_set_tuning with the build as a third dimension: threads =
+ * 512 or 256 selects the work-group size of the forward kernel (256 only
+ * takes effect where the plan fits that build: site matrices of at most 64
+ * rows with FP32 factorisations, 32 with FP64 ones, LDS within half a CU),
+ * 0 = automatic; wg_per_cu (<= 4) then caps that build's work-groups per CU.
+ * All zeros restore the default.  Returns TN_OK or TN_EINVAL. */
+int tn_set_tuning_ex(int32_t d, int32_t chi, int32_t precision, int32_t group, int32_t wg_per_cu, int32_t threads);
+
+/* HOST helper (needs a device): the launch shape a one-segment call of
+ * (d, chi, precision) uses now: shape[0] columns per site, shape[1]
+ * work-groups per CU, shape[2] threads per work-group.  shape: host int32[3]. */
+int tn_get_launch(int32_t d, int32_t chi, int32_t precision, int32_t* shape);
+
 /* Status of the last tn_coset_loglik / tn_decode_batch /
  * tn_coset_loglik_backward call that used `workspace` (its input-value checks
  * and numerical health, see "Errors" above).  Synchronises `stream` (the

@@ -386,9 +386,17 @@ def plan_info(d, chi, precision="fp32"):
                 gemm_flops=gemm[0], gemm_flops_syndrome=gemm[1])
 
 
-def set_tuning(d, chi, precision, group=0, wg_per_cu=0):
-    """Launch shape for (d, chi, precision); zeros restore the default."""
-    check_rc(lib().tn_set_tuning(d, chi, PRECISIONS[precision], group, wg_per_cu))
+def set_tuning(d, chi, precision, group=0, wg_per_cu=0, threads=0):
+    """Launch shape for (d, chi, precision): columns per site, work-groups per
+    CU, work-group size (512 or 256; 0 automatic); zeros restore the default."""
+    check_rc(lib().tn_set_tuning_ex(d, chi, PRECISIONS[precision], group, wg_per_cu, threads))
+
+
+def launch_shape(d, chi, precision):
+    """(group, wg_per_cu, threads) a one-segment call of this bucket uses now."""
+    out = (ctypes.c_int32 * 3)()
+    check_rc(lib().tn_get_launch(d, chi, PRECISIONS[precision], out))
+    return int(out[0]), int(out[1]), int(out[2])
 
 
 def code_stabilizers(d):

@@ -209,7 +209,7 @@ constexpr int kMaxWgPerCU = 1024 / NT > 1 ? 1024 / NT : 1;  // 4 waves per SIMD 
 
 // Tuned launch shapes, set by tn_set_tuning (the autotuner's cache).
 struct Tune {
-  int group, wgs;
+  int group, wgs, threads;  // threads: 0 = either build, 512 or 256 = that build
 };
 std::map<std::tuple<int, int, int>, Tune> g_tune;
 
@@ -422,7 +422,14 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
       if (!precision_built(prec)) return fail(TN_EUNSUPPORTED, "precision not built");
       DevPlan* dp = nullptr;
       if ((rc = get_plan(s.d, s.chi, prec, lds_limit, &dp, upload))) return rc;
-      if ((allow_small && small_plan(dp->plan.h, prec)) != small) continue;
+      Tune tu{0, 0, 0};
+      {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_tune.find(std::make_tuple(s.d, s.chi, prec));
+        if (it != g_tune.end()) tu = it->second;
+      }
+      const bool want_small = allow_small && tu.threads != NT && small_plan(dp->plan.h, prec);
+      if (want_small != small) continue;
       L.host_plan[L.jt.n] = &dp->plan;
       JobDev& j = L.jt.j[L.jt.n++];
       j.plan = dp->dev;
@@ -437,12 +444,8 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
       merge_maxima(&L.merged, dp->plan.h);
       L.scratch_elems = std::max<int64_t>(L.scratch_elems, dp->plan.h.scratch_elems);
       L.mps_elems = std::max<int64_t>(L.mps_elems, dp->plan.h.mps_elems);
-      int tw = 0;
-      {
-        std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_tune.find(std::make_tuple(s.d, s.chi, prec));
-        if (it != g_tune.end()) tw = it->second.wgs;
-      }
+      // a tuned work-groups-per-CU count applies to the build it was tuned on
+      const int tw = (tu.threads == (small ? kSmallNT : NT) || (tu.threads == 0 && !small)) ? tu.wgs : 0;
       if (tw > 0) L.nwg = L.nwg ? std::min(L.nwg, tw) : tw;  // per-CU count for now
     }
     L.jt.nitems = items;
@@ -457,6 +460,7 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
     if (L.small) {
       const int ws = tnmld_small::small_wgs_per_cu(L.precision, lb);
       w = std::min(kLdsPerCU / (lb + 256), ws > 0 ? ws : 1);
+      if (L.nwg > 0) w = std::min(w, L.nwg);  // tuned for the 256-thread build
     } else if (L.nwg > 0) {
       w = std::min(w, L.nwg);  // tuned work-groups per CU (tuned for the 512-thread build)
     }
@@ -881,13 +885,45 @@ int tn_plan_info(int32_t d, int32_t chi, int32_t precision, double* info) {
   return TN_OK;
 }
 
-int tn_set_tuning(int32_t d, int32_t chi, int32_t precision, int32_t group, int32_t wg_per_cu) {
+int tn_set_tuning_ex(int32_t d, int32_t chi, int32_t precision, int32_t group, int32_t wg_per_cu,
+                     int32_t threads) {
   if (d < 3 || d > TN_MAX_D || d % 2 == 0 || chi < 0 || precision < TN_FP64 || precision > TN_FP32_PLAIN ||
-      group < 0 || group > 2 || wg_per_cu < 0 || wg_per_cu > kMaxWgPerCU)
+      group < 0 || group > 2 || wg_per_cu < 0 || wg_per_cu > 4 || (threads != 0 && threads != NT && threads != kSmallNT))
     return fail(TN_EINVAL, "bad tuning arguments");
   std::lock_guard<std::mutex> lk(g_mu);
-  if (group == 0 && wg_per_cu == 0) g_tune.erase(std::make_tuple(d, chi, precision));
-  else g_tune[std::make_tuple(d, chi, precision)] = Tune{group, wg_per_cu};
+  if (group == 0 && wg_per_cu == 0 && threads == 0) g_tune.erase(std::make_tuple(d, chi, precision));
+  else g_tune[std::make_tuple(d, chi, precision)] = Tune{group, wg_per_cu, threads};
+  return TN_OK;
+}
+
+int tn_set_tuning(int32_t d, int32_t chi, int32_t precision, int32_t group, int32_t wg_per_cu) {
+  if (wg_per_cu > kMaxWgPerCU) return fail(TN_EINVAL, "bad tuning arguments");
+  return tn_set_tuning_ex(d, chi, precision, group, wg_per_cu, 0);
+}
+
+int tn_get_launch(int32_t d, int32_t chi, int32_t precision, int32_t* shape) {
+  if (!shape || precision < TN_FP64 || precision > TN_FP32_PLAIN) return fail(TN_EINVAL, "bad arguments");
+  // a one-segment call of this bucket: which build and how many groups per CU
+  tn_segment sg{};
+  sg.d = d;
+  sg.chi = chi;
+  sg.precision = precision;
+  sg.n_models = 1;
+  sg.count = 1;
+  sg.rates = reinterpret_cast<const double*>(1);  // never dereferenced: only the plan is built
+  sg.syndromes = reinterpret_cast<const uint8_t*>(1);
+  sg.out_logz = reinterpret_cast<double*>(1);
+  std::vector<Launch> launches;
+  size_t need = 0;
+  int nwg = 0;
+  DevInfo di;
+  int rc = device_info(&di);
+  if (rc) return rc;
+  if ((rc = plan_launches(&sg, 1, std::min(di.lds_max, kLdsLimit), &launches, &need, &nwg))) return rc;
+  if (launches.size() != 1) return fail(TN_EUNSUPPORTED, "no launch");
+  shape[0] = launches[0].host_plan[0]->h.group;
+  shape[1] = launches[0].nwg / std::max(1, di.cus);
+  shape[2] = launches[0].small ? kSmallNT : NT;
   return TN_OK;
 }
 

@@ -153,3 +153,17 @@ def test_planar_plan_counts(d):
     assert abs(info["log_pref"] - ((n - 1) // 2 - n) * np.log(2.0)) < 1e-12
     with pytest.raises(tn.TNError):
         tn.bitflip_plan_info(4)
+
+
+def test_tune_cache_entries_are_their_fastest_candidates():
+    """Every autotuner cache entry stores the launch shape of its fastest
+    timed candidate (the cache is the tuner's output, not edited by hand)."""
+    import json
+    from paper_2605_17230_amd import tune
+    with open(tune.DEFAULT_CACHE) as f:
+        cache = json.load(f)
+    assert cache["entries"]
+    for key, e in cache["entries"].items():
+        best = max(e["candidates"], key=lambda c: c["syndromes_per_s"])
+        assert (e["group"], e["wg_per_cu"], e["threads"]) == (best["group"], best["wg_per_cu"], best["threads"]), key
+        assert e["syndromes_per_s"] == best["syndromes_per_s"]

@@ -90,7 +90,9 @@ def environment():
                     break
     except OSError:
         pass
-    return {"gpu": torch.cuda.get_device_name(0), "rocm_hip": torch.version.hip, "torch": torch.__version__,
+    props = torch.cuda.get_device_properties(0)
+    return {"gpu": "%s (%s, %d CUs)" % (props.name, props.gcnArchName, props.multi_processor_count),
+            "rocm_hip": torch.version.hip, "torch": torch.__version__,
             "cpu": cpu, "nproc": os.cpu_count(),
             "omp_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
 
@@ -237,10 +239,11 @@ def bench_fit(a, torch, tn, synth, dev):
     # logical error rate on fresh syndromes of the generating model
     test = synth.sample(d, true_rates, 8192, 5002)
     tsyn = torch.from_numpy(test["syndromes"]).to(dev)
-    ler = {}
+    ler, held = {}, {}
     for name, th in (("true_prior", true), ("refit_prior_N=%d" % ns[-1], theta_last), ("start_prior", theta0)):
-        _, _, cls = tn.decode(tsyn, th.exp(), d, chi, prec)
+        _, lp, cls = tn.decode(tsyn, th.exp(), d, chi, prec)
         ler[name] = float((cls.cpu().numpy() != test["true_class"]).mean())
+        held[name] = float(-lp.mean())
     out = {
         "metric": "syndromes/s through the noise fit (forward + adjoint + Adam step) at d=11 chi=24",
         "value": rate, "unit": "syndromes/s", "n_gpus": 1, "steps": a.fit_steps,
@@ -252,6 +255,7 @@ def bench_fit(a, torch, tn, synth, dev):
         "start": {"mean_abs_log_rate_error": float((theta0 - true).abs().mean())},
         "rate_error_vs_N": per_n,
         "logical_error_rate_fresh_8192": ler,
+        "mean_neg_log_p_fresh_8192": held,
         "environment": environment(),
     }
     print(json.dumps(out), flush=True)
@@ -445,9 +449,12 @@ def main():
     ms_step = float(np.mean(ms))
     value = n_syn / (ms_step / 1e3)
     achieved = flops_per_step / (ms_step / 1e3) / 1e12
+    metric = {"c3": "syndromes/s at d=17 chi=32 (boundary-MPS coset decoding), BF16 form vs FP32 plain; "
+                    "coset log-likelihood error vs FP64",
+              "c2": "syndromes/s of the d=9 chi=16 p-sweep (boundary-MPS coset decoding, plain FP32)",
+              "c4": "syndromes/s of the mixed-distance batch d=5..15 (boundary-MPS coset decoding)"}[a.workload]
     out = {
-        "metric": "syndromes/s at d=17 chi=32 (boundary-MPS coset decoding), BF16 form vs FP32 plain; "
-                  "coset log-likelihood error vs FP64",
+        "metric": metric,
         "value": value,
         "unit": "syndromes/s",
         "n_gpus": 1,

@@ -10,6 +10,8 @@ Procedures (see the C file header for the passages they follow):
   transfer         O3, exact contraction over stabiliser variables
   rbim             O4, bit-flip noise as a random-bond Ising model
   grad_logp        O5, d log P(s) / d log p_{q,P}
+  phen_enum2       O6, phenomenological noise, T = 2 rounds, d = 3 (enumeration)
+  phen_transfer    O7, phenomenological noise, any T (exact transfer, small d)
 """
 from __future__ import annotations
 
@@ -56,6 +58,9 @@ def _load():
             "orc_rbim": (I, [I, D, P, P]),
             "orc_grad_logp": (I, [I, P, P, P, P]),
             "orc_decide": (I, [P, L, D, P, P]),
+            "orc_phen_enum2": (I, [I, P, P, P, L, P]),
+            "orc_phen_transfer": (I, [I, I, P, P, P, L, P, I]),
+            "orc_phen_max_bits": (I, [I, I]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(lib, name)
@@ -179,3 +184,41 @@ def decide(logz, tie_tol: float = 1e-9):
     c = np.zeros(b, np.uint8)
     _load().orc_decide(_p(z), b, float(tie_tol), _p(lp), _p(c))
     return lp, c
+
+
+def _phen_inputs(d, rounds, rates, meas, syndromes):
+    n, m = d * d, d * d - 1
+    r = _rates1(rates, n)
+    q = np.ascontiguousarray(meas, np.float64)
+    if q.shape != (m,):
+        raise ValueError("meas must be [m]")
+    s = np.ascontiguousarray(syndromes, np.uint8)
+    if s.ndim == 2:
+        s = s[None]
+    if s.shape[1:] != (rounds, m):
+        raise ValueError("syndromes must be [B, T, m]")
+    return r, q, s
+
+
+def phen_enum2(d: int, rates, meas, syndromes) -> np.ndarray:
+    """O6: logZ [B,4] under phenomenological noise with T = 2 rounds (d = 3);
+    syndromes [B, 2, m] (round 1 noisy, round 2 perfect), meas [m]."""
+    r, q, s = _phen_inputs(d, 2, rates, meas, syndromes)
+    out = np.zeros((s.shape[0], 4), np.float64)
+    _chk(_load().orc_phen_enum2(d, _p(r), _p(q), _p(s), s.shape[0], _p(out)), "phen_enum2")
+    return out
+
+
+def phen_transfer(d: int, rounds: int, rates, meas, syndromes, threads: int = 0) -> np.ndarray:
+    """O7: logZ [B,4] under phenomenological noise with T rounds; syndromes
+    [B, T, m] (rounds 1..T-1 noisy, round T perfect), meas [m]."""
+    r, q, s = _phen_inputs(d, rounds, rates, meas, syndromes)
+    out = np.zeros((s.shape[0], 4), np.float64)
+    _chk(_load().orc_phen_transfer(d, int(rounds), _p(r), _p(q), _p(s), s.shape[0], _p(out), int(threads)),
+         "phen_transfer")
+    return out
+
+
+def phen_state_bits(d: int, rounds: int) -> int:
+    """log2 of the O7 state size (its cost is 4^T times that per qubit)."""
+    return _chk(_load().orc_phen_max_bits(d, int(rounds)), "phen_max_bits")

@@ -27,6 +27,26 @@
  *                             marginals obtained by restricting qubit q to one
  *                             Pauli in O3 (the derivative of the likelihood in
  *                             eq. "dmle_loss").
+ *   O6 orc_phen_enum2       - phenomenological noise (Sec. 2.2, repeated noisy
+ *                             syndrome rounds), T = 2 rounds, d = 3: every
+ *                             first-round error, with the second round's
+ *                             errors summed through the O1 table.
+ *   O7 orc_phen_transfer    - the same distribution for any T (small d): the
+ *                             sum over every per-round error consistent with
+ *                             the measured syndromes, as a transfer over the
+ *                             qubits with the checks' partial parities as the
+ *                             state (the (2+1)-D problem of Sec. 3.2.3,
+ *                             computed exactly).
+ *
+ * Phenomenological model (O6, O7).  Rounds t = 1..T.  Before round t every
+ * qubit suffers E_t(q) with the code-capacity rates; C_t = E_1 ... E_t is the
+ * accumulated error.  Round t < T reports s_t = sigma(C_t) xor m_t, each check
+ * j flipped independently with probability meas[j]; round T is perfect,
+ * s_T = sigma(C_T).  The class is that of C_T.  With E_t = C_{t-1} C_t:
+ *     Z_l(s_1..s_T) = sum over C_1..C_T with sigma(C_T) = s_T and class(C_T) = l
+ *         of prod_t prod_q p_q(C_{t-1,q} C_{t,q})
+ *            * prod_{t<T} prod_j meas_j^{[s_tj != sigma_j(C_t)]} (1-meas_j)^{[s_tj == sigma_j(C_t)]},
+ * C_0 = I.
  *
  * Conventions: qubit q = r*d + c; Pauli 0=I,1=X,2=Y,3=Z (x-bit for X,Y; z-bit
  * for Y,Z); checks at corners (r,c) in [-1,d-1]^2, X-type iff r+c even; bulk
@@ -536,6 +556,191 @@ int orc_grad_logp(int d, const double* rates, const uint8_t* syn, double* grad, 
     }
     free(w);
     return 0;
+}
+
+/* ---------------------------------------------------------------- O6
+ * T = 2, d = 3.  Z_l = sum_{C_1} Pr(E_1 = C_1) Pr(m_1) * sum_{E_2} Pr(E_2)
+ * [sigma(C_1 E_2) = s_2, class(C_1 E_2) = l].  The inner sum is the O1 table
+ * entry of syndrome s_2 xor sigma(C_1) and class l xor class(C_1) (both are
+ * linear in the error).  syn: [2][m]; logZ[4]. */
+int orc_phen_enum2(int d, const double* rates, const double* meas, const uint8_t* syn, int64_t count, double* logZ) {
+    code_t C;
+    if (build_code(d, &C) || C.n > 12) return -1;
+    int n = C.n, m = C.m;
+    double w[4 * ORC_MAXN];
+    weights_from_rates(n, rates, w);
+    double* table = malloc(sizeof(double) * ((size_t)4 << m));
+    if (!table || orc_enumerate(d, rates, table, NULL)) {
+        free(table);
+        return -2;
+    }
+    uint8_t e[ORC_MAXN], s1[ORC_MAXM];
+    uint64_t total = (uint64_t)1 << (2 * n);
+    for (int64_t b = 0; b < count; ++b) {
+        const uint8_t* sy1 = syn + b * 2 * m;
+        const uint8_t* sy2 = sy1 + m;
+        size_t si2 = 0;
+        for (int j = 0; j < m; ++j) si2 |= (size_t)sy2[j] << j;
+        ksum_t acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+        for (uint64_t code = 0; code < total; ++code) {
+            double pr = 1.0;
+            for (int q = 0; q < n; ++q) {
+                e[q] = (uint8_t)((code >> (2 * q)) & 3);
+                pr *= w[4 * q + e[q]];
+            }
+            syndrome_of(&C, e, s1);
+            size_t si = 0;
+            for (int j = 0; j < m; ++j) {
+                pr *= (s1[j] != sy1[j]) ? meas[j] : 1.0 - meas[j];
+                si |= (size_t)s1[j] << j;
+            }
+            const int c1 = class_of(&C, e);
+            for (int l = 0; l < 4; ++l) {
+                const int l2 = pauli_of(xbit(l) ^ xbit(c1), zbit(l) ^ zbit(c1));
+                kadd(&acc[l], pr * table[(si2 ^ si) * 4 + l2]);
+            }
+        }
+        for (int l = 0; l < 4; ++l) {
+            double v = kval(&acc[l]);
+            logZ[4 * b + l] = v > 0.0 ? log(v) : -INFINITY;
+        }
+    }
+    free(table);
+    return 0;
+}
+
+/* ---------------------------------------------------------------- O7
+ * Any T (1 <= T <= 4), small d.  Qubits in row-major order; each qubit takes
+ * all 4^T histories (C_{1,q}..C_{T,q}) with weight prod_t p_q(C_{t-1,q} C_{t,q}).
+ * The state holds, for every open check (the slots of O3) and every round,
+ * the parity of sigma_j(C_t) over the qubits seen so far, plus the two class
+ * parities of C_T; a history XORs its contributions into the state.  When a
+ * check's last qubit is done, round t < T multiplies by the measurement
+ * probability of s_tj given the parity and round T keeps parity == s_Tj; the
+ * slot is then free (its bits back to 0).  psi is rescaled after every qubit.
+ * syn: [count][T][m]; meas: [m]; logZ: [count][4]. */
+static int phen_one(const code_t* C, const plan_t* P, int T, const double* w, const double* meas,
+                    const uint8_t* syn, double* psi, double* tmp, double* logZ) {
+    const int n = C->n, d = C->d;
+    const int sb = P->nslot * T, cb = sb;  /* class bits at cb (x, row 0) and cb + 1 (z, column 0) */
+    const size_t N = (size_t)1 << (sb + 2);
+    int slot_of[ORC_MAXM];
+    int slot_used[32] = {0};
+    for (size_t i = 0; i < N; ++i) psi[i] = 0.0;
+    psi[0] = 1.0;
+    double logscale = 0.0;
+    const int nh = 1 << (2 * T);
+    for (int q = 0; q < n; ++q) {
+        for (int k = 0; k < P->qn[q]; ++k) {
+            int j = P->qg[q][k];
+            if (P->first[j] == q) {
+                int s = 0;
+                while (slot_used[s]) ++s;
+                slot_used[s] = 1;
+                slot_of[j] = s;
+            }
+        }
+        for (size_t i = 0; i < N; ++i) tmp[i] = 0.0;
+        for (int h = 0; h < nh; ++h) {
+            /* history h: C_t = (h >> 2(t-1)) & 3 as a Pauli code, t = 1..T */
+            double wt = 1.0;
+            int prev = 0;
+            size_t mask = 0;
+            for (int t = 0; t < T; ++t) {
+                const int c = (h >> (2 * t)) & 3;
+                const int e = pauli_of(xbit(prev) ^ xbit(c), zbit(prev) ^ zbit(c));
+                wt *= w[4 * q + e];
+                prev = c;
+                for (int k = 0; k < P->qn[q]; ++k) {
+                    const int j = P->qg[q][k];
+                    const int flip = C->type[j] == 1 ? xbit(c) : zbit(c);
+                    if (flip) mask ^= (size_t)1 << (slot_of[j] * T + t);
+                }
+                if (t == T - 1) {
+                    if (q < d && xbit(c)) mask ^= (size_t)1 << cb;
+                    if (q % d == 0 && zbit(c)) mask ^= (size_t)1 << (cb + 1);
+                }
+            }
+            if (wt == 0.0) continue;
+            for (size_t i = 0; i < N; ++i)
+                if (psi[i] != 0.0) tmp[i ^ mask] += wt * psi[i];
+        }
+        for (size_t i = 0; i < N; ++i) psi[i] = tmp[i];
+        for (int k = 0; k < P->qn[q]; ++k) {
+            const int j = P->qg[q][k];
+            if (P->last[j] != q) continue;
+            const int s = slot_of[j];
+            const size_t smask = (((size_t)1 << T) - 1) << (s * T);
+            for (size_t i = 0; i < N; ++i) {
+                if (i & smask) continue;
+                double acc = 0.0;
+                for (int bits = 0; bits < (1 << T); ++bits) {
+                    const size_t ii = i | ((size_t)bits << (s * T));
+                    double g = 1.0;
+                    for (int t = 0; t < T; ++t) {
+                        const int par = (bits >> t) & 1, obs = syn[t * C->m + j];
+                        if (t < T - 1) g *= par != obs ? meas[j] : 1.0 - meas[j];
+                        else if (par != obs) g = 0.0;
+                    }
+                    acc += g * psi[ii];
+                }
+                for (int bits = 1; bits < (1 << T); ++bits) psi[i | ((size_t)bits << (s * T))] = 0.0;
+                psi[i] = acc;
+            }
+            slot_used[s] = 0;
+        }
+        double mx = 0.0;
+        for (size_t i = 0; i < N; ++i)
+            if (fabs(psi[i]) > mx) mx = fabs(psi[i]);
+        if (!(mx > 0.0)) {
+            for (int l = 0; l < 4; ++l) logZ[l] = -INFINITY;
+            return 0;
+        }
+        for (size_t i = 0; i < N; ++i) psi[i] /= mx;
+        logscale += log(mx);
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b2 = 0; b2 < 2; ++b2) {
+            const double v = psi[((size_t)a << cb) | ((size_t)b2 << (cb + 1))];
+            logZ[pauli_of(a, b2)] = v > 0.0 ? logscale + log(v) : -INFINITY;
+        }
+    return 0;
+}
+
+int orc_phen_max_bits(int d, int T) {
+    code_t C;
+    if (build_code(d, &C)) return -1;
+    plan_t P;
+    make_plan(&C, &P);
+    return P.nslot * T + 2;
+}
+
+int orc_phen_transfer(int d, int T, const double* rates, const double* meas, const uint8_t* syn, int64_t count,
+                      double* logZ, int nthreads) {
+    code_t C;
+    if (build_code(d, &C) || T < 1 || T > 4) return -1;
+    plan_t P;
+    make_plan(&C, &P);
+    if (P.nslot * T + 2 > 26) return -1;
+    int n = C.n, m = C.m;
+    double w[4 * ORC_MAXN];
+    weights_from_rates(n, rates, w);
+    const size_t N = (size_t)1 << (P.nslot * T + 2);
+    int err = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t b = 0; b < count; ++b) {
+        double* psi = malloc(sizeof(double) * N);
+        double* tmp = malloc(sizeof(double) * N);
+        if (!psi || !tmp) err = -2;
+        else phen_one(&C, &P, T, w, meas, syn + b * (int64_t)T * m, psi, tmp, logZ + 4 * b);
+        free(psi);
+        free(tmp);
+    }
+    (void)nthreads;
+    return err;
 }
 
 /* ---------------------------------------------------------------- decisions

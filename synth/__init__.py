@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "code_checks", "depolarizing", "bitflip", "phaseflip", "biased",
     "inhomogeneous", "sample_errors", "syndromes_of", "classes_of", "sample",
-    "CONFIGS", "config_inputs",
+    "sample_phenom", "CONFIGS", "config_inputs",
 ]
 
 
@@ -142,6 +142,37 @@ def sample(d: int, rates: np.ndarray, count: int, seed: int,
     return dict(errors=err, syndromes=syndromes_of(d, err), true_class=classes_of(d, err),
                 model_index=np.ascontiguousarray(model_index, dtype=np.int32),
                 rates=np.ascontiguousarray(rates))
+
+
+def _pauli_xor(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Product of Pauli codes (phases dropped) as codes."""
+    lut = np.array([[0, 1, 2, 3], [1, 0, 3, 2], [2, 3, 0, 1], [3, 2, 1, 0]], dtype=np.uint8)
+    return lut[a, b]
+
+
+def sample_phenom(d: int, rates: np.ndarray, meas: np.ndarray, rounds: int, count: int, seed: int):
+    """Phenomenological noise (repeated noisy syndrome rounds): before each of
+    the T rounds every qubit draws a Pauli with the code-capacity rates; rounds
+    1..T-1 report the syndrome of the accumulated error with each check flipped
+    independently with probability meas[j]; round T is perfect.  Returns
+    dict(syndromes [B, T, m], true_class [B] of the accumulated error,
+    errors [B, T, n] per round, flips [B, T-1, m])."""
+    rates = np.asarray(rates, dtype=np.float64)
+    meas = np.asarray(meas, dtype=np.float64)
+    n, m = d * d, d * d - 1
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cum = np.cumsum(np.concatenate([1.0 - rates.sum(-1, keepdims=True), rates], -1), -1)  # [n, 4]
+    u = rng.random((count, rounds, n))
+    err = (u[..., None] >= cum[None, None, :, :3]).sum(-1).astype(np.uint8)
+    flips = (rng.random((count, max(rounds - 1, 0), m)) < meas[None, None, :]).astype(np.uint8)
+    syn = np.zeros((count, rounds, m), np.uint8)
+    acc = np.zeros((count, n), np.uint8)
+    for t in range(rounds):
+        acc = _pauli_xor(acc, err[:, t])
+        syn[:, t] = syndromes_of(d, acc)
+        if t < rounds - 1:
+            syn[:, t] ^= flips[:, t]
+    return dict(syndromes=syn, true_class=classes_of(d, acc), errors=err, flips=flips)
 
 
 # ----------------------------------------------------------------- workloads

@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--precision", default=None,
                     help="form timed (default: bf16; fp32plain for c2, as that workload names; fp32 for c5 and fit)")
     ap.add_argument("--compare", default="fp32plain", help="second form timed once ('' to skip)")
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5", "fit", "study", "planar"])
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5", "fit", "study", "planar", "rounds"])
     ap.add_argument("--study-count", type=int, default=4096, help="syndromes per (d, p) point of the study")
     ap.add_argument("--fit-steps", type=int, default=60, help="Adam steps of the fit workload")
     ap.add_argument("--fit-batch", type=int, default=1024, help="syndromes per step of the fit workload")
@@ -368,6 +368,69 @@ def bench_planar(a, torch, tn, synth, dev, stream):
     print(json.dumps(out), flush=True)
 
 
+def bench_rounds(a, torch, tn, synth, dev, stream):
+    """Repeated noisy rounds (phenomenological noise): d = 7, T = 2 rounds
+    (the first with measurement flips at q = 0.02, the last perfect),
+    depolarizing p = 0.02 per round, 16,384 seeded histories, chi = 16 (12 in
+    the FP64-factorisation forms); against the exact phenomenological oracle
+    on a sample."""
+    import oracle
+    d, p, q, T, n = 7, 0.02, 0.02, 2, a.count
+    chi = 12 if a.precision in ("fp64", "fp32") else 16
+    rates = synth.depolarizing(d, p)
+    meas = np.full(d * d - 1, q)
+    smp = synth.sample_phenom(d, rates, meas, T, n, 7000)
+    syn, rt, mq = (torch.from_numpy(smp["syndromes"]).to(dev), torch.from_numpy(rates).to(dev),
+                   torch.from_numpy(meas).to(dev))
+    info = tn.plan_info(d, chi, a.precision, rounds=T)
+    print("bench: two-round decoding d=%d T=%d p=q=%.2f chi=%d %s, %d histories" % (d, T, p, chi, a.precision, n),
+          file=sys.stderr, flush=True)
+    W = __import__("warnings")
+    with W.catch_warnings():
+        W.simplefilter("ignore", tn.api.UnresolvedCosetsWarning)
+        for _ in range(a.warmup):
+            tn.decode_rounds(syn, rt, mq, d, chi, a.precision)
+        torch.cuda.synchronize()
+        ev = []
+        for _ in range(a.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            lz, lp, cls = tn.decode_rounds(syn, rt, mq, d, chi, a.precision)
+            e1.record(stream)
+            ev.append((e0, e1))
+        torch.cuda.synchronize()
+    ms = float(np.mean([x.elapsed_time(y) for x, y in ev]))
+    flops = n * info["flops_syndrome"]
+    ach = flops / (ms / 1e3) / 1e12
+    lz, lp, cls = lz.cpu().numpy(), lp.cpu().numpy(), cls.cpu().numpy()
+    out = {
+        "metric": "histories/s of two-round (phenomenological) decoding at d=7",
+        "value": n / (ms / 1e3), "unit": "histories/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[a.precision], "data": "synthetic",
+        "config": {"workload": "rotated surface code d=7, 2 syndrome rounds (first with check flips q=0.02, last "
+                               "perfect), depolarizing p=0.02 per round, %d seeded histories, chi=%d" % (n, chi),
+                   "precision": a.precision},
+        "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach / PEAK_ALU_TFLOPS, "traffic": None, "flops_per_launch": flops,
+                     "kernel": "fwd_kernel"},
+        "logical_error_rate": float((cls != smp["true_class"]).mean()),
+        "environment": environment(),
+    }
+    if not a.no_cpu:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        k = min(4 * max(threads, 1), n)  # about 10 s of oracle work on 16 cores
+        t0 = time.time()
+        ref = oracle.phen_transfer(d, T, rates, meas, smp["syndromes"][:k], threads=threads)
+        dt = time.time() - t0
+        out["cpu_baseline"] = {"value": k / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
+                               "sample": "first %d histories, exact FP64 transfer over the qubits, %.1f s" % (k, dt)}
+        lpo, clo = oracle.decide(ref)
+        out["parity_vs_oracle"] = {"histories": k, "max_abs_dlogp": float(np.max(np.abs(lpo - lp[:k]))),
+                                   "class_agreement": float((clo == cls[:k]).mean())}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -395,6 +458,9 @@ def main():
         return
     if a.workload == "planar":
         bench_planar(a, torch, tn, synth, dev, stream)
+        return
+    if a.workload == "rounds":
+        bench_rounds(a, torch, tn, synth, dev, stream)
         return
     if a.workload == "c3":
         rates = synth.depolarizing(D, P)

@@ -45,6 +45,21 @@
  * syndrome (improbable cosets whose weight the truncated, rounded boundary
  * state cannot carry), and the call counts them (tn_workspace_status).  With
  * some rates zero, -INFINITY may be exact and is not recorded.
+ *
+ * Repeated noisy rounds (phenomenological noise, Sec. 2.2; the (2+1)-D
+ * problem of Sec. 3.2.3).  A segment with rounds = T >= 2 holds T syndromes
+ * per item: before each round every qubit suffers a Pauli error drawn from the
+ * segment's rates (the same rates every round), rounds 1..T-1 report the
+ * syndrome of the accumulated error with check j flipped independently with
+ * probability meas_rates[j], and round T is perfect.  Z_l sums the probability
+ * of every error history (per-round errors and measurement flips) that
+ * reproduces the T syndromes and leaves an accumulated error of class l.  It is
+ * contracted as the same boundary MPS with every column carrying one check
+ * variable per round (2^T values): the first T-1 rounds' variables are the
+ * Fourier duals of the measurement weights, the last round's the generator
+ * variables of the code-capacity network, and each qubit's tensor sums its
+ * T-1 intermediate accumulated Paulis.  The time direction is thus exact;
+ * T <= TN_MAX_ROUNDS.  The gradient entry point takes rounds <= 1 only.
  */
 #ifndef TNMLD_H
 #define TNMLD_H
@@ -83,6 +98,7 @@ typedef enum {
 
 #define TN_MAX_D 31
 #define TN_MAX_SEGMENTS 16
+#define TN_MAX_ROUNDS 2
 
 /* One homogeneous group of syndromes: one code distance, one bond dimension,
  * one precision, and a set of noise models addressed by model_index. */
@@ -98,6 +114,12 @@ typedef struct {
   double* out_logz;            /* device [count][4]: natural-log Z_l; required */
   double* out_logp;            /* device [count]: log P(s) = logsumexp_l log Z_l, or NULL */
   uint8_t* out_class;          /* device [count]: tie-tolerant argmax, or NULL */
+  int32_t rounds;              /* 0 or 1: one perfect round (code capacity).  2..TN_MAX_ROUNDS: repeated noisy
+                                  rounds (above); syndromes are then [count][rounds][d*d-1], round-major per
+                                  item, and the chosen bond dimension applies to the wider columns */
+  int32_t reserved;            /* 0 */
+  const double* meas_rates;    /* device [n_models][d*d-1]: flip probability of each check's measurement in
+                                  rounds 1..T-1, in [0, 1]; used (and required) when rounds >= 2 */
 } tn_segment;
 
 /* Bytes of device workspace that tn_coset_loglik / tn_decode_batch need for
@@ -161,6 +183,10 @@ int tn_code_stabilizers(int32_t d, int32_t* type_out, int32_t* support_out);
  * the four cosets once, the rest four times).
  * info: host array of >= 8 doubles.  Returns TN_OK or a tn_status. */
 int tn_plan_info(int32_t d, int32_t chi, int32_t precision, double* info);
+
+/* HOST helper: tn_plan_info for segments with `rounds` syndrome rounds (the
+ * plan of the repeated-rounds network; rounds <= 1 is tn_plan_info). */
+int tn_plan_info_rounds(int32_t d, int32_t chi, int32_t precision, int32_t rounds, double* info);
 
 /* HOST helper: the GEMM-class part of the counted forward work of the plan
  * for (d, chi, precision): the MPO-applied site times the carried factor, the

@@ -18,6 +18,7 @@ TN_OK, TN_EINVAL, TN_ENOMEM, TN_EDEVICE, TN_EUNSUPPORTED, TN_ENUMERIC = 0, -1, -
 TN_FP64, TN_FP32, TN_BF16, TN_FP32_PLAIN = 0, 1, 2, 3
 PRECISIONS = {"fp64": TN_FP64, "fp32": TN_FP32, "bf16": TN_BF16, "fp32plain": TN_FP32_PLAIN}
 TN_MAX_SEGMENTS = 16
+TN_MAX_ROUNDS = 2
 
 
 class Segment(ctypes.Structure):
@@ -26,6 +27,7 @@ class Segment(ctypes.Structure):
         ("n_models", ctypes.c_int32), ("rates", ctypes.c_void_p), ("model_index", ctypes.c_void_p),
         ("syndromes", ctypes.c_void_p), ("count", ctypes.c_int64), ("out_logz", ctypes.c_void_p),
         ("out_logp", ctypes.c_void_p), ("out_class", ctypes.c_void_p),
+        ("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32), ("meas_rates", ctypes.c_void_p),
     ]
 
 
@@ -58,6 +60,8 @@ def lib():
         L.tn_code_stabilizers.argtypes = [I32, P, P]
         L.tn_plan_info.restype = ctypes.c_int
         L.tn_plan_info.argtypes = [I32, I32, I32, ctypes.POINTER(D)]
+        L.tn_plan_info_rounds.restype = ctypes.c_int
+        L.tn_plan_info_rounds.argtypes = [I32, I32, I32, I32, ctypes.POINTER(D)]
         L.tn_plan_gemm_flops.restype = ctypes.c_int
         L.tn_plan_gemm_flops.argtypes = [I32, I32, I32, ctypes.POINTER(D)]
         L.tn_set_tuning.restype = ctypes.c_int

@@ -61,11 +61,12 @@ def _need_cuda(t, name):
         raise ValueError("%s must be a CUDA (HIP) tensor" % name)
 
 
-def check_input_values(syndromes, rates, model_index=None):
+def check_input_values(syndromes, rates, model_index=None, meas_rates=None):
     """Value checks of one segment's inputs (any device; one host read-back):
     syndrome bytes in {0, 1}, model indices in [0, M), rates in [0, 1] with no
-    NaN and p_X + p_Y + p_Z <= 1 + 1e-12 per qubit.  Raises ValueError.  The
-    kernels repeat these checks per syndrome (tn_workspace_status)."""
+    NaN and p_X + p_Y + p_Z <= 1 + 1e-12 per qubit, measurement flip rates (if
+    given) in [0, 1].  Raises ValueError.  The kernels repeat these checks per
+    syndrome (tn_workspace_status)."""
     r = rates if rates.dim() == 3 else rates.unsqueeze(0)
     flags = [(syndromes > 1).any()]
     ok01 = (r >= 0) & (r <= 1)  # False for NaN
@@ -75,9 +76,13 @@ def check_input_values(syndromes, rates, model_index=None):
         flags.append((model_index < 0).any() | (model_index >= r.shape[0]).any())
     else:
         flags.append(torch.zeros((), dtype=torch.bool, device=r.device))
+    if meas_rates is not None:
+        flags.append(~((meas_rates >= 0) & (meas_rates <= 1)).all())
+    else:
+        flags.append(torch.zeros((), dtype=torch.bool, device=r.device))
     bad = torch.stack([f.to(torch.bool).reshape(()) for f in flags]).tolist()
     what = ["a syndrome byte above 1", "a rate outside [0, 1] or NaN", "p_X + p_Y + p_Z above 1",
-            "a model index outside [0, %d)" % r.shape[0]]
+            "a model index outside [0, %d)" % r.shape[0], "a measurement flip rate outside [0, 1] or NaN"]
     msg = [w for w, b in zip(what, bad) if b]
     if msg:
         raise ValueError("invalid decoder inputs: " + ", ".join(msg))
@@ -92,6 +97,8 @@ class SegmentInput:
     rates: torch.Tensor                # float64 [M, d*d, 3] (or [d*d, 3]) on the GPU
     model_index: torch.Tensor | None = None  # int32 [B] or None
     precision: str = "fp32"
+    rounds: int = 1                    # T >= 2: repeated noisy rounds, syndromes [B, T, d*d-1], last round perfect
+    meas_rates: torch.Tensor | None = None  # float64 [M, d*d-1] (or [d*d-1]): check flip rates of rounds 1..T-1
 
 
 @dataclass
@@ -110,9 +117,16 @@ def _prepare(segs, check=True):
         _need_cuda(s.syndromes, "syndromes")
         _need_cuda(s.rates, "rates")
         n, m = s.d * s.d, s.d * s.d - 1
+        T = int(s.rounds) if s.rounds else 1
+        if not 1 <= T <= _lib.TN_MAX_ROUNDS:
+            raise ValueError("rounds must be in [1, %d]" % _lib.TN_MAX_ROUNDS)
         syn = s.syndromes.to(torch.uint8).contiguous()
-        if syn.dim() != 2 or syn.shape[1] != m:
-            raise ValueError("syndromes must be [B, d*d-1]")
+        if T > 1 and syn.dim() == 3:
+            if syn.shape[1:] != (T, m):
+                raise ValueError("syndromes must be [B, T, d*d-1]")
+            syn = syn.reshape(syn.shape[0], T * m)
+        if syn.dim() != 2 or syn.shape[1] != m * T:
+            raise ValueError("syndromes must be [B, d*d-1]" if T == 1 else "syndromes must be [B, T, d*d-1]")
         rates = s.rates.to(torch.float64).contiguous()
         if rates.dim() == 2:
             rates = rates.unsqueeze(0)
@@ -124,8 +138,18 @@ def _prepare(segs, check=True):
             mi = s.model_index.to(torch.int32).contiguous()
             if mi.shape != (syn.shape[0],):
                 raise ValueError("model_index must be [B]")
+        meas = None
+        if T > 1:
+            if s.meas_rates is None:
+                raise ValueError("repeated rounds need meas_rates")
+            _need_cuda(s.meas_rates, "meas_rates")
+            meas = s.meas_rates.to(torch.float64).contiguous()
+            if meas.dim() == 1:
+                meas = meas.unsqueeze(0)
+            if meas.shape != (rates.shape[0], m):
+                raise ValueError("meas_rates must be [M, d*d-1]")
         if check:
-            check_input_values(syn, rates, mi)
+            check_input_values(syn, rates, mi, meas)
         b = syn.shape[0]
         dev = syn.device
         o = SegmentOutput(torch.empty((b, 4), dtype=torch.float64, device=dev),
@@ -133,9 +157,10 @@ def _prepare(segs, check=True):
                           torch.empty(b, dtype=torch.uint8, device=dev))
         arr[i] = Segment(s.d, s.chi, PRECISIONS[s.precision], rates.shape[0], rates.data_ptr(),
                          mi.data_ptr() if mi is not None else None, syn.data_ptr(), b,
-                         o.logz.data_ptr(), o.logp.data_ptr(), o.cls.data_ptr())
+                         o.logz.data_ptr(), o.logp.data_ptr(), o.cls.data_ptr(),
+                         T, 0, meas.data_ptr() if meas is not None else None)
         outs.append(o)
-        keep += [t for t in (syn, rates, mi) if t is not None]
+        keep += [t for t in (syn, rates, mi, meas) if t is not None]
     return arr, outs, keep
 
 
@@ -227,6 +252,15 @@ def decode(syndromes, rates, d, chi, precision="fp32", model_index=None, tie_tol
     return o.logz, o.logp, o.cls
 
 
+def decode_rounds(syndromes, rates, meas_rates, d, chi, precision="fp32", model_index=None, tie_tol=1e-9):
+    """Repeated noisy rounds: syndromes [B, T, d*d-1] (rounds 1..T-1 with check
+    flips at meas_rates [M, d*d-1], round T perfect), rates [M, d*d, 3].
+    Returns (logz [B,4], logp [B], class [B]) of the accumulated error."""
+    T = int(syndromes.shape[1])
+    o = decode_segments([SegmentInput(d, chi, syndromes, rates, model_index, precision, T, meas_rates)], tie_tol)[0]
+    return o.logz, o.logp, o.cls
+
+
 def coset_loglik(syndromes, rates, d, chi, precision="fp32", model_index=None, check=True):
     """log Z_l(s) [B,4] and log P(s) [B]."""
     do_check = check and not torch.cuda.is_current_stream_capturing()
@@ -253,6 +287,8 @@ def coset_loglik_backward(segs, grad_logp, stream=None, outputs=None, workspace_
     (outputs, grads) with grads[i] float64 [M, d*d, 3] (a fresh zeroed tensor
     that the library accumulates into).  stream, workspace_buf, check: as for
     decode_segments."""
+    if any((s.rounds or 1) > 1 for s in segs):
+        raise ValueError("the gradient takes segments of one syndrome round")
     do_check = bool(check) and not torch.cuda.is_current_stream_capturing()
     arr, outs, keep = _prepare(segs, do_check and check != "device")
     forward_done = 0
@@ -376,9 +412,9 @@ def bitflip_plan_info(d):
     return dict(order=int(info[0]), nnz=int(info[1]), lu_flops=info[2], scratch_bytes=info[3], log_pref=info[4])
 
 
-def plan_info(d, chi, precision="fp32"):
+def plan_info(d, chi, precision="fp32", rounds=1):
     info = (ctypes.c_double * 8)()
-    check_rc(lib().tn_plan_info(d, chi, PRECISIONS[precision], info))
+    check_rc(lib().tn_plan_info_rounds(d, chi, PRECISIONS[precision], int(rounds), info))
     gemm = (ctypes.c_double * 2)()
     check_rc(lib().tn_plan_gemm_flops(d, chi, PRECISIONS[precision], gemm))
     return dict(flops=info[0], scratch_bytes=info[1], lds_bytes=info[2], sites=int(info[3]),

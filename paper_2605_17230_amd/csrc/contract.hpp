@@ -26,8 +26,9 @@ struct JobDev {
   int64_t item_begin;
   int64_t part_ofs;     // backward: offset of this segment in a work-group's partial gradient
   int32_t n_models;
-  int32_t pad;
+  int32_t rounds;       // syndrome rounds per item (0 or 1: one perfect round)
   unsigned* status;     // status word of the call (ST_* bits), in the workspace header
+  const double* meas;   // repeated rounds: [n_models][m] measurement flip probabilities
 };
 
 struct JobTable {
@@ -51,6 +52,41 @@ __device__ inline Real pauli_weight(const double* rq, int fb, int P) {
   return Real(rq[e - 1]);
 }
 
+// Repeated rounds: the qubit tensor of code 2 + k (see the MPO code comment
+// in plan.hpp), in FP64.  rq: the qubit's rates; fb: bits of f_q.
+__device__ inline double pauli_prob2(const double* rq, int c) {  // c = x | z << 1
+  if (c == 0) return fmax(1.0 - rq[0] - rq[1] - rq[2], 0.0);
+  return rq[c == 1 ? 0 : (c == 3 ? 1 : 2)];
+}
+__device__ inline double rounds_tensor(const double* rq, int fb, int k, int T) {
+  const int dT = (k >> (2 * (T - 1))) & 3;
+  const int cT = dT ^ fb;  // C_T = f_q P_T as (x | z << 1)
+  double acc = 0.0;
+  const int nh = 1 << (2 * (T - 1));
+  for (int h = 0; h < nh; ++h) {  // intermediate accumulated Paulis C_1..C_{T-1}
+    double prod = 1.0;
+    int prev = 0, sgn = 0;
+    for (int t = 0; t < T - 1; ++t) {
+      const int c = (h >> (2 * t)) & 3;
+      const int dg = (k >> (2 * t)) & 3;  // (bX, bZ) of round t+1
+      prod *= pauli_prob2(rq, prev ^ c);
+      sgn ^= ((dg & 1) & (c >> 1)) ^ ((dg >> 1) & (c & 1));
+      prev = c;
+    }
+    prod *= pauli_prob2(rq, prev ^ cT);
+    acc += sgn ? -prod : prod;
+  }
+  return acc;
+}
+// Measurement weights of check j carried by the T-bit variable value `idx`:
+// prod over rounds t < T-1 of g(bit t), g(0) = 1/2, g(1) = (1 - 2 q_j)/2 (-1)^{s_tj}.
+__device__ inline double rounds_check_weight(const double* meas, const uint8_t* syn, int m, int j, int idx, int T) {
+  double v = 1.0;
+  const double h1 = 0.5 * (1.0 - 2.0 * meas[j]);
+  for (int t = 0; t < T - 1; ++t) v *= ((idx >> t) & 1) ? (syn[t * m + j] ? -h1 : h1) : 0.5;
+  return v;
+}
+
 // Bits a call ORs into the status word of its workspace.  The status word is
 // followed (8 bytes on) by a 64-bit count of unresolved cosets.
 enum : unsigned {
@@ -68,6 +104,9 @@ struct ItemCheck {
   bool positive;  // every Pauli of every qubit has probability > 0: every coset then has Z > 0
 };
 
+// Syndrome rounds of a job's items (at least 1) and the bytes of one item.
+__device__ inline int job_rounds(const JobDev& job) { return job.rounds > 1 ? job.rounds : 1; }
+
 // Input check of syndrome b (collective): syndrome bytes in {0, 1}, model
 // index in [0, n_models), and the model's rates in [0, 1] (NaN fails) with
 // p_X + p_Y + p_Z <= 1.  An invalid item raises ST_BAD_INPUT.
@@ -76,9 +115,14 @@ __device__ inline ItemCheck check_item(const JobDev& job, int64_t b, int n, int 
   const int raw = job.model_index ? job.model_index[b] : 0;
   const bool mok = raw >= 0 && raw < job.n_models;
   const int model = mok ? raw : 0;
-  const uint8_t* sy = job.syn + b * m;
+  const int R = job_rounds(job);
+  const uint8_t* sy = job.syn + b * (int64_t)m * R;
   int bad = mok ? 0 : 1;
-  for (int j = tid; j < m; j += NT) bad |= sy[j] > 1 ? 1 : 0;
+  for (int j = tid; j < m * R; j += NT) bad |= sy[j] > 1 ? 1 : 0;
+  if (R > 1) {  // measurement flip probabilities in [0, 1] (NaN fails)
+    const double* mq = job.meas + (int64_t)model * m;
+    for (int j = tid; j < m; j += NT) bad |= (mq[j] >= 0.0 && mq[j] <= 1.0) ? 0 : 1;
+  }
   const double* r = job.rates + (int64_t)model * n * 3;
   int pos = 1;
   for (int q = tid; q < n; q += NT) {
@@ -146,6 +190,11 @@ struct Work {
   Fac *X, *tau, *diag, *vtmp, *Mm, *Vv, *Lt, *sig;
   int* s_flag;
   int* s_dead;
+  // repeated rounds (rounds > 1): the item's syndromes (round-major) and its
+  // model's measurement flip probabilities
+  int rounds, msyn;
+  const uint8_t* syn_rounds;
+  const double* meas;
 };
 
 template <typename Real, typename Fac>
@@ -171,6 +220,10 @@ __device__ inline Work<Real, Fac> carve(uint8_t* smem, const LdsLayout& lay, int
   w.sig = reinterpret_cast<Fac*>(smem + lay.sig);
   w.s_flag = flags;
   w.s_dead = flags + 1;
+  w.rounds = 1;
+  w.msyn = 0;
+  w.syn_rounds = nullptr;
+  w.meas = nullptr;
   return w;
 }
 
@@ -266,18 +319,27 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
       const int RB = Dr * B, nn = qo * kr;
       const int ncode = A * qi * qo * B;
       const uint8_t* cd = codes + st.wofs;
-      if (tid < ncode) {
+      for (int e = tid; e < ncode; e += NT) {
         // plan order [a][si][so][b]; a transposed row reads the forward code [a][so][si][b]
-        int ci = tid;
+        int ci = e;
         if (st.tr) {
-          const int bb = tid % B, so = (tid / B) % qo, si = (tid / (B * qo)) % qi, a = tid / (B * qo * qi);
+          const int bb = e % B, so = (e / B) % qo, si = (e / (B * qo)) % qi, a = e / (B * qo * qi);
           ci = ((a * qo + so) * qi + si) * B + bb;
         }
         const int c = cd[ci];
         Real v = Real(0);
-        if (c == W_ONE) v = Real(1);
-        else if (c >= W_PAULI) v = pauli_weight<Real>(rates + 3 * st.q, fbits[st.q], c - W_PAULI);
-        Wv[tid] = v;
+        if (w.rounds <= 1) {
+          if (c == W_ONE) v = Real(1);
+          else if (c >= W_PAULI) v = pauli_weight<Real>(rates + 3 * st.q, fbits[st.q], c - W_PAULI);
+        } else if (c != W_ZERO) {
+          // forward rows only (the gradient takes one round)
+          const int so = (e / B) % qo, si = (e / (B * qo)) % qi;
+          double x = c == W_ONE ? 1.0 : rounds_tensor(rates + 3 * st.q, fbits[st.q], c - W_PAULI, w.rounds);
+          if (st.wnew >= 0) x *= rounds_check_weight(w.meas, w.syn_rounds, w.msyn, st.wnew, so, w.rounds);
+          if (st.wold >= 0) x *= rounds_check_weight(w.meas, w.syn_rounds, w.msyn, st.wold, si, w.rounds);
+          v = Real(x);
+        }
+        Wv[e] = v;
       }
       Real* g = scr + region[J];
       const Real* As = Aj ? Aj : g;  // LDS copy, or the site region itself (its L2 lines)
@@ -285,11 +347,12 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
         for (int e = tid; e < Dl * qi * Dr; e += NT) Aj[e] = g[e];
       __syncthreads();
       const int ldp = (RB + 7) & ~7;  // plane row length (BF16 form)
+      const int sA = A == 4 ? 2 : (A == 2 ? 1 : 0), sB = B == 4 ? 2 : (B == 2 ? 1 : 0);
       for (int so = 0; so < qo; ++so) {
         // T[(l,a)][(r,b)] = sum_si Aj[l][si][r] W[a][si][so][b]
-        // (A and B, the MPO bonds, are 1 or 2)
+        // (A and B, the MPO bonds, are 1, 2 or 4)
         auto tval = [&](int la, int rb) {
-          const int l = A == 2 ? la >> 1 : la, a = la & (A - 1), r = B == 2 ? rb >> 1 : rb, bb = rb & (B - 1);
+          const int l = la >> sA, a = la & (A - 1), r = rb >> sB, bb = rb & (B - 1);
           Real acc = 0;
           for (int si = 0; si < qi; ++si)
             acc += As[(l * qi + si) * Dr + r] * Wv[((a * qi + si) * qo + so) * B + bb];
@@ -533,6 +596,16 @@ __device__ void contract_syndrome(const JobDev& job, int64_t b, uint8_t* smem, c
     return;
   }
   const double* rates = job.rates + (int64_t)ck.model * n * 3;
+  // the reference error comes from the last (perfect) round's syndrome
+  const int R = job_rounds(job);
+  const uint8_t* syn_b = job.syn + b * (int64_t)m * R;
+  const uint8_t* syn_last = syn_b + (int64_t)(R - 1) * m;
+  if (R > 1) {
+    w.rounds = R;
+    w.msyn = m;
+    w.syn_rounds = syn_b;
+    w.meas = job.meas + (int64_t)ck.model * m;
+  }
   const SiteStep* rowS = steps + (int64_t)ushare * nsite;
   auto dims = [rowS](int J, int& Dl, int& q, int& Dr) {
     Dl = rowS[J].Dl_old;
@@ -540,7 +613,7 @@ __device__ void contract_syndrome(const JobDev& job, int64_t b, uint8_t* smem, c
     Dr = rowS[J].Dr_old;
   };
   // common prefix (coset 0's reference error; the others differ only later)
-  prep_reference(H, checks, job.syn + b * m, 0, w.syn, w.fbits, &s_label);
+  prep_reference(H, checks, syn_last, 0, w.syn, w.fbits, &s_label);
   mps_ones(scr, region, plan + H->init_qi_ofs, nsite);
   double base = 0.0;
   bool alive = true;
@@ -548,7 +621,7 @@ __device__ void contract_syndrome(const JobDev& job, int64_t b, uint8_t* smem, c
     alive = row_step<Real, Fac, GM>(steps + (int64_t)u * nsite, nsite, codes, rates, scr, region, w, base);
   if (!alive) {
     for (int mlog = 0; mlog < 4; ++mlog) {
-      const int label = prep_reference(H, checks, job.syn + b * m, mlog, w.syn, w.fbits, &s_label);
+      const int label = prep_reference(H, checks, syn_last, mlog, w.syn, w.fbits, &s_label);
       if (threadIdx.x == 0) job.logz[b * 4 + label] = -INFINITY;
       __syncthreads();
     }
@@ -559,7 +632,7 @@ __device__ void contract_syndrome(const JobDev& job, int64_t b, uint8_t* smem, c
   int dead = 0;  // thread 0: cosets written as -inf
   for (int mlog = 0; mlog < 4; ++mlog) {
     if (mlog > 0) mps_pack(scr, region, nsite, dims, snap, true, scr);
-    const int label = prep_reference(H, checks, job.syn + b * m, mlog, w.syn, w.fbits, &s_label);
+    const int label = prep_reference(H, checks, syn_last, mlog, w.syn, w.fbits, &s_label);
     double logscale = base;
     bool ok = true;
     for (int u = ushare; u < nstep && ok; ++u)

@@ -426,6 +426,7 @@ int kw_validate(const tn_segment* segs, int32_t nseg) {
     if (s.n_models < 1) return kfail(TN_EINVAL, "n_models must be >= 1");
     if (s.count < 0) return kfail(TN_EINVAL, "count must be >= 0");
     if (s.count > 0 && (!s.rates || !s.syndromes || !s.out_logz)) return kfail(TN_EINVAL, "null pointer");
+    if (s.rounds > 1) return kfail(TN_EINVAL, "the planar exact solver takes one syndrome round");
   }
   return TN_OK;
 }

@@ -53,11 +53,14 @@ inline double svd_flops(double M, double N) {  // dense SVD model 6 M N^2 + 20 N
 
 }  // namespace
 
-std::string build_plan(int d, int chi, int group, Plan* out) {
+std::string build_plan(int d, int chi, int group, Plan* out, int rounds) {
   if (d < 3 || d > 31 || (d % 2) == 0) return "d must be odd, 3 <= d <= 31";
   if (chi < 0 || chi > 4096) return "chi out of range";
   if (group < 1 || group > 2) return "group must be 1 or 2";
+  if (rounds < 1 || rounds > 2) return "rounds must be 1 or 2";
+  if (rounds > 1 && group != 1) return "repeated rounds need one column per site";
   Layout L{d};
+  const int V = 1 << rounds;  // values of one column variable (a bit per round)
   const int P = 2 * d - 1;  // columns
   const int nsite = (P + group - 1) / group;
   const int nstep = 2 * d - 1;
@@ -87,6 +90,24 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
   h.lx_col = d - 1;
   h.lz_row = d - 1;
   h.shared_rows = std::min(h.lx_col, h.lz_row);
+  h.rounds = rounds;
+  // syndrome index of the check with corner (r, c): Z-type checks first, then
+  // X-type, each by corner (the order of the check descriptors below)
+  std::vector<int> check_id((size_t)(d + 1) * (d + 1), -1);
+  {
+    int j = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int r = -1; r <= d - 1; ++r)
+        for (int c = -1; c <= d - 1; ++c) {
+          if (!L.exists(r, c)) continue;
+          if ((pass == 0) == (((r + c) & 1) == 0)) continue;
+          check_id[(size_t)(r + 1) * (d + 1) + (c + 1)] = j++;
+        }
+  }
+  auto check_of = [&](int sum, int w) {  // check of the variable at corner sum `sum`, column w
+    const int r = (sum - w) / 2, c = (sum + w) / 2;
+    return check_id[(size_t)(r + 1) * (d + 1) + (c + 1)];
+  };
 
   // variables before step 0: column w holds corner sum -2 (w even) or -1 (w odd)
   for (int J = 0; J < nsite; ++J) {
@@ -94,7 +115,7 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
     for (int i = site_lo(J); i < site_hi(J); ++i) {
       int w = wcol(i);
       bool v = ((w & 1) == 0) ? L.var(-2, w) : L.var(-1, w);
-      if (v) qi *= 2;
+      if (v) qi *= V;
     }
     init_qi[J] = (uint8_t)qi;
   }
@@ -120,10 +141,10 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
     for (int J = 0; J + 1 < nsite; ++J) {
       int iL = site_hi(J) - 1, iR = iL + 1;
       if (act[iL] && qub[iL] >= 0 && vin[iR]) {
-        bond[J] = 2;
+        bond[J] = V;
         owner[J] = J + 1;
       } else if (act[iR] && qub[iR] >= 0 && vin[iL]) {
-        bond[J] = 2;
+        bond[J] = V;
         owner[J] = J;
       }
     }
@@ -135,8 +156,8 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
       int qi = 1, qo = 1;
       int bit_in[2] = {-1, -1}, bit_out[2] = {-1, -1};
       for (int i = lo; i < hi; ++i) {
-        if (vin[i]) bit_in[i - lo] = __builtin_ctz(qi), qi *= 2;
-        if (vout[i]) bit_out[i - lo] = __builtin_ctz(qo), qo *= 2;
+        if (vin[i]) bit_in[i - lo] = __builtin_ctz(qi), qi *= V;
+        if (vout[i]) bit_out[i - lo] = __builtin_ctz(qo), qo *= V;
       }
       int ia = -1;
       for (int i = lo; i < hi; ++i)
@@ -148,21 +169,28 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
       S.qo = (uint8_t)qo;
       S.act = (uint8_t)(ia >= 0 ? ia - lo : 0);
       S.wofs = (int32_t)codes.size();
+      S.wnew = S.wold = -1;
+      if (rounds > 1 && ia >= 0) {
+        const int w = wcol(ia);
+        if (vout[ia]) S.wnew = (int16_t)check_of(u, w);
+        if (vin[ia] && u - 2 < 0) S.wold = (int16_t)check_of(u - 2, w);
+      }
+      h.max_ncode = std::max(h.max_ncode, A * qi * qo * B);
       for (int a = 0; a < A; ++a)
         for (int si = 0; si < qi; ++si)
           for (int so = 0; so < qo; ++so)
             for (int b = 0; b < B; ++b) {
-              auto bin = [&](int i) { int k = bit_in[i - lo]; return k < 0 ? 0 : (si >> k) & 1; };
-              auto bout = [&](int i) { int k = bit_out[i - lo]; return k < 0 ? 0 : (so >> k) & 1; };
+              auto bin = [&](int i) { int k = bit_in[i - lo]; return k < 0 ? 0 : (si >> k) & (V - 1); };
+              auto bout = [&](int i) { int k = bit_out[i - lo]; return k < 0 ? 0 : (so >> k) & (V - 1); };
               bool ok = true;
               for (int i = lo; i < hi; ++i)
                 if (!act[i] && bin(i) != bout(i)) ok = false;
               int ext_l = 0, ext_r = 0;
-              if (A == 2) {
+              if (A > 1) {
                 if (owner[J - 1] == J) { if (a != bin(lo)) ok = false; }
                 else ext_l = a;
               }
-              if (B == 2) {
+              if (B > 1) {
                 if (owner[J] == J) { if (b != bin(hi - 1)) ok = false; }
                 else ext_r = b;
               }
@@ -182,7 +210,13 @@ std::string build_plan(int d, int chi, int group, Plan* out) {
                   int x, z;
                   if ((u & 1) == 0) { x = N ^ Sv; z = c2; }
                   else { x = c2; z = N ^ Sv; }
-                  code = (uint8_t)(W_PAULI + pauli_of(x, z));
+                  if (rounds == 1) {
+                    code = (uint8_t)(W_PAULI + pauli_of(x, z));
+                  } else {
+                    int k = 0;  // digit t: (x, z) bits of round t+1
+                    for (int t = 0; t < rounds; ++t) k |= ((((x >> t) & 1) | (((z >> t) & 1) << 1)) << (2 * t));
+                    code = (uint8_t)(W_PAULI + k);
+                  }
                 }
               }
               codes.push_back(code);
@@ -453,6 +487,7 @@ void merge_maxima(PlanHeader* a, const PlanHeader& h) {
   a->max_rows = std::max(a->max_rows, h.max_rows);
   a->max_bond = std::max(a->max_bond, h.max_bond);
   a->max_envb = std::max(a->max_envb, h.max_envb);
+  a->max_ncode = std::max(a->max_ncode, h.max_ncode);
   a->tmp_elems = std::max(a->tmp_elems, h.tmp_elems);
   a->n = std::max(a->n, h.n);
   a->m = std::max(a->m, h.m);

@@ -41,14 +41,27 @@ struct SiteStep {
   int16_t k;               // rows kept by its LQ factorisation: min(m, qo * kr)
   int16_t kr;              // k of the site to the right (1 for the last site)
   int16_t Dl_new, Dr_new;  // bonds after truncation
-  int16_t pad1;
+  int16_t wnew;            // repeated rounds: check whose variable this site creates (its measurement
+                           // weights multiply the MPO entries through the output index), -1 if none
   int32_t wofs;            // offset of the A*qi*qo*B MPO code table
-  int32_t pad2;
+  int16_t wold;            // repeated rounds: check whose variable existed before row 0 and ends at this
+                           // site (weights through the input index), -1 if none
+  int16_t pad2;
 };
 static_assert(sizeof(SiteStep) == 32, "SiteStep layout");
 
 // Code of one MPO entry: 0 -> 0, 1 -> 1, 2 + P -> p_q(f_q xor P), P in {I,X,Y,Z}
 // (xor on the (x,z) bit pair).  Entry order: [a][si][so][b].
+//
+// Repeated rounds (T >= 2).  A column variable is a T-bit tuple, bit t the
+// check's variable in round t+1: for t < T-1 the dual variable b of its
+// measurement weight, g(b) = 1/2 (b = 0) or (1 - 2 q_j)/2 (-1)^{s_tj} (b = 1),
+// so that sum_b g(b) (-1)^{b x} = Pr(s_tj | parity x); for t = T-1 the
+// generator variable.  2 + k then codes the qubit's tensor
+//   sum over C_1..C_{T-1} of prod_{t=1..T} p_q(C_{t-1} C_t)
+//       * prod_{t<T} (-1)^{bX_t z(C_t) + bZ_t x(C_t)},   C_0 = I, C_T = f_q P_T,
+// with k = sum_t 4^t (x_t + 2 z_t): digit t < T-1 holds the XORs (bX, bZ) of the
+// round's X-type and Z-type neighbour variables, digit T-1 the Pauli P_T.
 enum : uint8_t { W_ZERO = 0, W_ONE = 1, W_PAULI = 2 };
 
 // Reference error R(s) = product over fired checks of a string that flips that
@@ -91,9 +104,10 @@ struct PlanHeader {  // device-visible, followed by the tables at the offsets be
   int32_t max_Q;    // k * qo * kr                    staged orthonormal site
   int32_t max_kr, max_n, max_m, max_rows, max_bond;
   int32_t max_envb;     // one bond of a row environment (adjoint): top bond * MPO bond * bottom bond
-  int32_t pad_h;
+  int32_t rounds;       // syndrome rounds T of the network (1: code capacity)
   int32_t shared_rows;  // rows 0..shared_rows-1 touch no qubit of the logical representatives:
                         // their MPOs, hence the MPS after them, are the same for all four cosets
+  int32_t max_ncode;    // entries of the largest MPO code table (A*qi*qo*B)
   double flops_fwd;     // counted flops of one coset's contraction (see count in plan.cpp)
   double flops_shared;  // the part of flops_fwd spent in rows 0..shared_rows-1
   double flops_gemm;         // GEMM-class part of flops_fwd (T.L, C.Q, and Q.W on truncated bonds)
@@ -106,7 +120,8 @@ struct Plan {
 };
 
 // Build the plan; returns an empty string on success, else an error message.
-std::string build_plan(int d, int chi, int group, Plan* out);
+// rounds >= 2 (repeated noisy rounds) needs group = 1.
+std::string build_plan(int d, int chi, int group, Plan* out, int rounds = 1);
 
 // Element-wise maximum of the LDS maxima of two plans (for one launch that
 // serves several plans).
@@ -184,7 +199,7 @@ inline LdsLayout lds_layout(const PlanHeader& h, int rb, int fb, bool aj_global 
       o.gP = 0;
     }
   }
-  o.W = p; p += pad64b(64 * rb);
+  o.W = p; p += pad64b((int64_t)(h.max_ncode > 64 ? h.max_ncode : 64) * rb);
   o.red = p; p += 64 * 8;
   o.nrm = p; p += pad64b((int64_t)(h.max_kr > h.max_bond ? h.max_kr : h.max_bond) * 8);
   o.perm = p; p += pad64b((int64_t)h.max_kr * 4);

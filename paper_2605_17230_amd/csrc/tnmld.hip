@@ -169,7 +169,7 @@ struct DevPlan {
 };
 
 std::mutex g_mu;
-std::map<std::tuple<int, int, int, int>, DevPlan*> g_plans;  // (device, d, chi, group)
+std::map<std::tuple<int, int, int, int, int>, DevPlan*> g_plans;  // (device, d, chi, group, rounds)
 
 struct DevInfo {
   int cus = 0;
@@ -266,9 +266,9 @@ int wgs_for(int lds_bytes, const void* kern = nullptr) {
 
 // Choose the column grouping (1 or 2 columns per site): a tuned entry if one
 // exists, else the grouping that fits the most work-groups per CU (ties: 2).
-int choose_group(int d, int chi, int precision, int lds_limit, Plan* out, std::string* why) {
-  int forced = 0;
-  {
+int choose_group(int d, int chi, int precision, int lds_limit, Plan* out, std::string* why, int rounds = 1) {
+  int forced = rounds > 1 ? 1 : 0;  // repeated rounds: one column (2^T values) per site
+  if (rounds <= 1) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_tune.find(std::make_tuple(d, chi, precision));
     if (it != g_tune.end()) forced = it->second.group;
@@ -278,7 +278,7 @@ int choose_group(int d, int chi, int precision, int lds_limit, Plan* out, std::s
   for (int g = 2; g >= 1; --g) {
     if (forced && g != forced) continue;
     Plan p;
-    std::string e = build_plan(d, chi, g, &p);
+    std::string e = build_plan(d, chi, g, &p, rounds);
     if (!e.empty()) {
       *why = e;
       return -1;
@@ -302,15 +302,15 @@ int choose_group(int d, int chi, int precision, int lds_limit, Plan* out, std::s
 // Plans are kept per (device, d, chi, group).  upload = false: the plan is
 // built and kept on the host only (dev stays null), for the allocation-free
 // entry point, which copies the blob into its own fixed device array.
-int get_plan(int d, int chi, int precision, int lds_limit, DevPlan** out, bool upload = true) {
+int get_plan(int d, int chi, int precision, int lds_limit, DevPlan** out, bool upload = true, int rounds = 1) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(TN_EDEVICE, "no HIP device");
   Plan p;
   std::string why;
-  int g = choose_group(d, chi, precision, lds_limit, &p, &why);
+  int g = choose_group(d, chi, precision, lds_limit, &p, &why, rounds);
   if (g < 0) return fail(TN_EUNSUPPORTED, why);
   std::lock_guard<std::mutex> lk(g_mu);
-  auto key = std::make_tuple(dev, d, chi, g);
+  auto key = std::make_tuple(dev, d, chi, g, rounds);
   auto it = g_plans.find(key);
   if (it != g_plans.end() && (it->second->dev || !upload)) {
     *out = it->second;
@@ -346,6 +346,8 @@ int validate(const tn_segment* segs, int32_t nseg) {
     if (s.n_models < 1) return fail(TN_EINVAL, "n_models must be >= 1");
     if (s.count < 0) return fail(TN_EINVAL, "count must be >= 0");
     if (s.count > 0 && (!s.rates || !s.syndromes || !s.out_logz)) return fail(TN_EINVAL, "null pointer");
+    if (s.rounds < 0 || s.rounds > TN_MAX_ROUNDS) return fail(TN_EINVAL, "rounds must be in [0, TN_MAX_ROUNDS]");
+    if (s.rounds > 1 && s.count > 0 && !s.meas_rates) return fail(TN_EINVAL, "repeated rounds need meas_rates");
   }
   return TN_OK;
 }
@@ -421,9 +423,10 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
       if (s.precision != prec || s.count == 0) continue;
       if (!precision_built(prec)) return fail(TN_EUNSUPPORTED, "precision not built");
       DevPlan* dp = nullptr;
-      if ((rc = get_plan(s.d, s.chi, prec, lds_limit, &dp, upload))) return rc;
+      const int rounds = s.rounds > 1 ? s.rounds : 1;
+      if ((rc = get_plan(s.d, s.chi, prec, lds_limit, &dp, upload, rounds))) return rc;
       Tune tu{0, 0, 0};
-      {
+      if (rounds == 1) {  // the tuned shapes are for one-round plans
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_tune.find(std::make_tuple(s.d, s.chi, prec));
         if (it != g_tune.end()) tu = it->second;
@@ -440,6 +443,8 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
       j.count = s.count;
       j.item_begin = items;
       j.n_models = s.n_models;
+      j.rounds = rounds;
+      j.meas = rounds > 1 ? s.meas_rates : nullptr;
       items += s.count;
       merge_maxima(&L.merged, dp->plan.h);
       L.scratch_elems = std::max<int64_t>(L.scratch_elems, dp->plan.h.scratch_elems);
@@ -637,6 +642,8 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
   DevInfo di;
   int rc = validate(segs, nseg);
   if (rc) return rc;
+  for (int i = 0; i < nseg; ++i)
+    if (segs[i].rounds > 1) return fail(TN_EUNSUPPORTED, "the gradient takes segments of one syndrome round");
   if ((rc = device_info(&di))) return rc;
   bl->hdr_bytes = kAlign;  // counters and the status word
   if ((rc = plan_launches(segs, nseg, std::min(di.lds_max, kLdsLimit), &launches, &fwd, &nwgf, false))) return rc;
@@ -864,10 +871,16 @@ int tn_plan_gemm_flops(int32_t d, int32_t chi, int32_t precision, double* out) {
 }
 
 int tn_plan_info(int32_t d, int32_t chi, int32_t precision, double* info) {
-  if (!info || precision < TN_FP64 || precision > TN_FP32_PLAIN) return fail(TN_EINVAL, "bad arguments");
+  return tn_plan_info_rounds(d, chi, precision, 1, info);
+}
+
+int tn_plan_info_rounds(int32_t d, int32_t chi, int32_t precision, int32_t rounds, double* info) {
+  if (!info || precision < TN_FP64 || precision > TN_FP32_PLAIN || rounds < 0 || rounds > TN_MAX_ROUNDS)
+    return fail(TN_EINVAL, "bad arguments");
+  if (rounds < 1) rounds = 1;
   Plan p;
   std::string why;
-  int g = choose_group(d, chi, precision, kLdsLimit, &p, &why);
+  int g = choose_group(d, chi, precision, kLdsLimit, &p, &why, rounds);
   if (g < 0) return fail(TN_EUNSUPPORTED, why);
   info[0] = p.h.flops_fwd;
   info[1] = (double)p.h.scratch_elems * real_bytes(precision);
@@ -877,7 +890,7 @@ int tn_plan_info(int32_t d, int32_t chi, int32_t precision, double* info) {
   info[5] = g;
   info[6] = wgs_for((int)info[2], fwd_kernel_of(precision));
   info[7] = p.h.flops_shared + 4.0 * (p.h.flops_fwd - p.h.flops_shared);
-  {
+  if (rounds == 1) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_tune.find(std::make_tuple(d, chi, precision));
     if (it != g_tune.end() && it->second.wgs > 0) info[6] = std::min<double>(info[6], it->second.wgs);

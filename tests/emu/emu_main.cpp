@@ -40,13 +40,15 @@ void run_block(F f) {
 
 template <typename Real, typename Fac>
 int forward(int d, int chi, int group, const double* rates, int n_models, const int32_t* model_index,
-            const uint8_t* syn, int count, double* logz, unsigned* status) {
+            const uint8_t* syn, int count, double* logz, unsigned* status, int rounds = 1,
+            const double* meas = nullptr) {
   Plan p;
-  if (!build_plan(d, chi, group, &p).empty()) return -1;
+  if (!build_plan(d, chi, group, &p, rounds).empty()) return -1;
   const LdsLayout lay = lds_layout(p.h, sizeof(Real), sizeof(Fac));
   std::vector<double> smem(lay.bytes / 8 + 16), scr(p.h.scratch_elems * sizeof(Real) / 8 + 16),
       snap(p.h.mps_elems * sizeof(Real) / 8 + 16);
-  JobDev job{p.blob.data(), rates, model_index, syn, logz, nullptr, nullptr, count, 0, 0, n_models, 0, status};
+  JobDev job{p.blob.data(), rates, model_index, syn, logz, nullptr, nullptr, count, 0, 0, n_models, rounds, status,
+             meas};
   Barriers bars;
   for (int b = 0; b < count; ++b)
     run_block([&](int) {
@@ -94,6 +96,16 @@ extern "C" int emu_forward_models(int d, int chi, int precision, int group, cons
   if (precision == 1)
     return forward<float, double>(d, chi, group, rates, n_models, model_index, syn, count, logz, status);
   return forward<float, float>(d, chi, group, rates, n_models, model_index, syn, count, logz, status);
+}
+
+// repeated noisy rounds (group 1): syndromes [count][rounds][m], meas [m]
+extern "C" int emu_forward_rounds(int d, int chi, int precision, int rounds, const double* rates, const double* meas,
+                                  const uint8_t* syn, int count, double* logz, unsigned* status) {
+  if (precision == 0)
+    return forward<double, double>(d, chi, 1, rates, 1, nullptr, syn, count, logz, status, rounds, meas);
+  if (precision == 1)
+    return forward<float, double>(d, chi, 1, rates, 1, nullptr, syn, count, logz, status, rounds, meas);
+  return forward<float, float>(d, chi, 1, rates, 1, nullptr, syn, count, logz, status, rounds, meas);
 }
 
 extern "C" int emu_gradient(int d, int chi, int precision, int group, const double* rates, const uint8_t* syn,

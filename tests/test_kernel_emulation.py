@@ -32,6 +32,7 @@ def emu():
     L.emu_forward.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_int, P]
     L.emu_gradient.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_int, P, P, P, P]
     L.emu_forward_models.argtypes = [ctypes.c_int] * 4 + [P, ctypes.c_int, P, P, ctypes.c_int, P, P]
+    L.emu_forward_rounds.argtypes = [ctypes.c_int] * 4 + [P, P, P, ctypes.c_int, P, P]
     return L
 
 
@@ -143,3 +144,24 @@ def test_numeric_status_only_for_positive_models(emu):
     assert st == ST_UNRESOLVED and np.isfinite(out[0, 0]) and np.isneginf(out[0, 1:]).all()
     out64, st64 = forward_models(emu, d, 0, 0, tiny, np.zeros(1), syn)  # FP64 keeps log P(s)
     assert not (st64 & ST_NUMERIC) and np.isfinite(np.logaddexp.reduce(out64, 1)).all()
+
+
+def test_d3_two_rounds_exact(emu):
+    """Repeated noisy rounds (T = 2, last round perfect): the kernel source's
+    column variables with one bit per round, the measurement weights as
+    Fourier duals and the qubit tensors summed over the intermediate
+    accumulated Pauli, untruncated at d = 3 in FP64, against the exact
+    phenomenological oracle O7 (itself pinned by enumeration, sampled
+    frequencies and total probability)."""
+    d, m = 3, 8
+    r = synth.inhomogeneous(d, 0.01, 0.1, seed=1)
+    q = np.linspace(0.02, 0.12, m)
+    smp = synth.sample_phenom(d, r, q, 2, 2, seed=2)
+    syn = np.ascontiguousarray(smp["syndromes"], np.uint8)
+    out = np.zeros((2, 4))
+    st = np.zeros(4, np.uint32)
+    assert emu.emu_forward_rounds(d, 0, 0, 2, r.ctypes.data, q.ctypes.data, syn.ctypes.data, 2, out.ctypes.data,
+                                  st.ctypes.data) == 0
+    ref = oracle.phen_transfer(d, 2, r, q, syn)
+    assert st[0] == 0
+    assert np.max(np.abs(out - ref) / np.maximum(1.0, np.abs(ref))) < 1e-12

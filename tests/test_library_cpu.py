@@ -41,7 +41,8 @@ def _seg(**kw):
 
 
 @pytest.mark.parametrize("bad", [dict(d=4), dict(d=1), dict(d=33), dict(chi=-1), dict(precision=7),
-                                 dict(n_models=0), dict(count=-2), dict(syndromes=None), dict(out_logz=None)])
+                                 dict(n_models=0), dict(count=-2), dict(syndromes=None), dict(out_logz=None),
+                                 dict(rounds=3), dict(rounds=-1), dict(rounds=2, meas_rates=None)])
 def test_invalid_arguments_rejected_before_device(L, bad):
     arr = (_lib.Segment * 1)(_seg(**bad))
     rc = L.tn_coset_loglik(arr, 1, None, 0, None)
@@ -167,3 +168,47 @@ def test_tune_cache_entries_are_their_fastest_candidates():
         best = max(e["candidates"], key=lambda c: c["syndromes_per_s"])
         assert (e["group"], e["wg_per_cu"], e["threads"]) == (best["group"], best["wg_per_cu"], best["threads"]), key
         assert e["syndromes_per_s"] == best["syndromes_per_s"]
+
+
+def test_rounds_plans():
+    """Plans of the repeated-rounds network (T = 2): one column per site, more
+    counted work than one round at the same chi, and the LDS limits of each
+    form (the FP64 factorisations of chi = 16 do not fit a CU)."""
+    import paper_2605_17230_amd as tn
+    for d, chi in [(3, 0), (5, 12), (9, 12)]:
+        one = tn.plan_info(d, chi, "fp64")
+        two = tn.plan_info(d, chi, "fp64", rounds=2)
+        assert two["group"] == 1 and two["flops"] > one["flops"] and two["rows"] == one["rows"]
+    assert tn.plan_info(17, 16, "fp32plain", rounds=2)["lds_bytes"] <= 160 * 1024
+    with pytest.raises(tn.TNError):
+        tn.plan_info(9, 16, "fp64", rounds=2)
+    with pytest.raises(tn.TNError):
+        tn.plan_info(9, 8, "fp64", rounds=3)
+
+
+def test_rounds_input_checks():
+    import torch
+    import paper_2605_17230_amd as tn
+    import synth
+    d = 5
+    r = torch.from_numpy(synth.depolarizing(d, 0.05))
+    q = torch.full((d * d - 1,), 0.05, dtype=torch.float64)
+    smp = synth.sample_phenom(d, r.numpy(), q.numpy(), 2, 4, seed=1)
+    syn = torch.from_numpy(smp["syndromes"].reshape(4, -1))
+    tn.check_input_values(syn, r, None, q)
+    bad = q.clone()
+    bad[3] = float("nan")
+    with pytest.raises(ValueError):
+        tn.check_input_values(syn, r, None, bad)
+    bad[3] = 1.5
+    with pytest.raises(ValueError):
+        tn.check_input_values(syn, r, None, bad)
+
+
+def test_gradient_rejects_repeated_rounds(L):
+    """tn_coset_loglik_backward takes one syndrome round: a two-round segment
+    is refused with TN_EUNSUPPORTED before any device call."""
+    arr = (_lib.Segment * 1)(_seg(rounds=2, meas_rates=1))
+    g = (ctypes.c_void_p * 1)(1)
+    rc = L.tn_coset_loglik_backward(arr, 1, g, g, 0, None, 0, None)
+    assert rc == _lib.TN_EUNSUPPORTED

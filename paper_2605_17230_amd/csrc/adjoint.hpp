@@ -1,6 +1,10 @@
 // Gradient of log Z_l(s) with respect to the per-qubit Pauli rates, by
 // environments of the boundary-MPS contraction (paper Sec. 3.2.4: the
-// contraction is differentiable in the local error probabilities).
+// contraction is differentiable in the local error probabilities).  With FP32
+// data the GEMM-shaped environment contractions (top site with the left
+// environment, bottom site with the right one, and the new environments) run
+// on the FP32 matrix cores; the small ones (through the MPO values, inner
+// size <= 8) and the derivative fold stay on the vector units.
 //
 // Z is linear in every qubit tensor, so d log Z / d w_q = Env_q / Z where
 // Env_q is the network with the tensor of qubit q removed.  For the row u that
@@ -8,9 +12,9 @@
 // MPS before row u, Phi_u the bottom boundary MPS contracted upwards through
 // rows u+1.. with transposed row MPOs, and T_u the row MPO.  Left and right
 // environments along the row give every site's derivative tensor; the overall
-// scale cancels in the ratio.  Psi is checkpointed every K rows on the way
-// down and each segment of K rows is recomputed from its checkpoint while the
-// bottom MPS climbs back up.
+// scale cancels in the ratio.  The top sweep keeps Psi_{u-1} for every row
+// (the rows common to the four cosets once), so the bottom MPS climbs back up
+// with no recomputation of the top states.
 #pragma once
 #include "contract.hpp"
 
@@ -32,6 +36,12 @@ __device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
                              double weight, double* part, uint8_t* smem, const LdsLayout& lay,
                              int64_t tmp_elems) {
   const int tid = threadIdx.x;
+  // FP32 data: the GEMM-shaped contractions run on the matrix cores
+#ifndef TNMLD_EMU
+  constexpr bool MF = sizeof(Real) == 4;
+#else
+  constexpr bool MF = false;
+#endif
   Real* P1 = lay.gP >= 0 ? reinterpret_cast<Real*>(smem + lay.gP) : P1g;
   Real* P2 = lay.gP >= 0 ? P1 + tmp_elems : P2g;
   Real* P3 = lay.gP >= 0 ? P2 + tmp_elems : P3g;
@@ -77,6 +87,23 @@ __device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
   };
   // physical dimensions are 1, 2 or 4 and MPO bonds 1 or 2: index splits are shifts
   auto lg = [](int x) { return x == 4 ? 2 : (x == 2 ? 1 : 0); };
+  // P[a][lF][si][rA] = sum_lA E[lA][a][lF] A[lA][si][rA] (E of DlA x (Aa DlF), A of DlA x qi x DrA)
+  auto contract_ea = [&](const Real* E, const Real* Aj, Real* P, int Aa, int DlF, int qi, int DlA, int DrA, int lqi) {
+    if constexpr (MF) {
+      const int me = Aa * DlF;
+      gemm_mfma_f32(
+          qi, me, DrA, DlA, [&](int, int i, int k) { return (float)E[k * me + i]; },
+          [&](int si, int k, int j) { return (float)Aj[(k * qi + si) * DrA + j]; },
+          [&](int si, int i, int j, float v) { P[(i * qi + si) * DrA + j] = Real(v); });
+    } else {
+      for_2d(Aa * DlF * qi, DrA, [&](int row, int rA) {
+        const int si = row & (qi - 1), t = row >> lqi, a = t >= DlF ? 1 : 0, lF = t - a * DlF;
+        Real acc = 0;
+        for (int lA = 0; lA < DlA; ++lA) acc += E[(lA * Aa + a) * DlF + lF] * Aj[(lA * qi + si) * DrA + rA];
+        P[row * DrA + rA] = acc;
+      });
+    }
+  };
   // bond sizes of the environment at bond J (left of site J)
   auto envb = [&](int J) {
     const int dt = J < nsite ? frow[J].Dl_old : 1, a = J < nsite ? frow[J].A : 1, db = J < nsite ? brow[J].Dl_old : 1;
@@ -105,12 +132,7 @@ __device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
     __syncthreads();
     const int lqi = lg(qi), lqo = lg(qo), lB = lg(B);
     // P1[a][lF][si][rA] = sum_lA E[lA][a][lF] A[lA][si][rA]
-    for_2d(Aa * DlF * qi, DrA, [&](int row, int rA) {
-      const int si = row & (qi - 1), t = row >> lqi, a = t >= DlF ? 1 : 0, lF = t - a * DlF;
-      Real acc = 0;
-      for (int lA = 0; lA < DlA; ++lA) acc += E[(lA * Aa + a) * DlF + lF] * Aj[(lA * qi + si) * DrA + rA];
-      P1[row * DrA + rA] = acc;
-    });
+    contract_ea(E, Aj, P1, Aa, DlF, qi, DlA, DrA, lqi);
     __syncthreads();
     // P2[lF][so][b][rA] = sum_{a,si} P1[a][lF][si][rA] W[a][si][so][b]
     for_2d(DlF * qo * B, DrA, [&](int row, int rA) {
@@ -123,13 +145,20 @@ __device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
     });
     __syncthreads();
     // En[rA][b][rF] = sum_{lF,so} P2[lF][so][b][rA] F[lF][so][rF]
-    for_2d(DrA * B, DrF, [&](int row, int rF) {
-      const int b = row & (B - 1), rA = row >> lB;
-      Real acc = 0;
-      for (int lF = 0; lF < DlF; ++lF)
-        for (int so = 0; so < qo; ++so) acc += P2[((lF * qo + so) * B + b) * DrA + rA] * Fj[(lF * qo + so) * DrF + rF];
-      En[row * DrF + rF] = acc;
-    });
+    if constexpr (MF) {
+      gemm_mfma_f32(
+          B, DrA, DrF, DlF * qo, [&](int b, int i, int k) { return (float)P2[(k * B + b) * DrA + i]; },
+          [&](int, int k, int j) { return (float)Fj[k * DrF + j]; },
+          [&](int b, int i, int j, float v) { En[(i * B + b) * DrF + j] = Real(v); });
+    } else {
+      for_2d(DrA * B, DrF, [&](int row, int rF) {
+        const int b = row & (B - 1), rA = row >> lB;
+        Real acc = 0;
+        for (int lF = 0; lF < DlF; ++lF)
+          for (int so = 0; so < qo; ++so) acc += P2[((lF * qo + so) * B + b) * DrA + rA] * Fj[(lF * qo + so) * DrF + rF];
+        En[row * DrF + rF] = acc;
+      });
+    }
     __syncthreads();
   }
   const double S = (double)env[s_eoff[nsite]];
@@ -160,21 +189,24 @@ __device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
     __syncthreads();
     const int lqi = lg(qi), lqo = lg(qo), lB = lg(B), lA_ = lg(Aa);
     // P1r[lF][so][rA][b] = sum_rF F[lF][so][rF] R[rA][b][rF]
-    for_2d(DlF * qo, DrA * B, [&](int row, int col) {
-      const int b = col & (B - 1), rA = col >> lB;
-      Real acc = 0;
-      for (int rF = 0; rF < DrF; ++rF) acc += Fj[row * DrF + rF] * R[(rA * B + b) * DrF + rF];
-      P1[row * (DrA * B) + col] = acc;
-    });
+    if constexpr (MF) {
+      const int nc = DrA * B;
+      gemm_mfma_f32(
+          1, DlF * qo, nc, DrF, [&](int, int i, int k) { return (float)Fj[i * DrF + k]; },
+          [&](int, int k, int j) { return (float)R[j * DrF + k]; },
+          [&](int, int i, int j, float v) { P1[i * nc + j] = Real(v); });
+    } else {
+      for_2d(DlF * qo, DrA * B, [&](int row, int col) {
+        const int b = col & (B - 1), rA = col >> lB;
+        Real acc = 0;
+        for (int rF = 0; rF < DrF; ++rF) acc += Fj[row * DrF + rF] * R[(rA * B + b) * DrF + rF];
+        P1[row * (DrA * B) + col] = acc;
+      });
+    }
     __syncthreads();
     if (st.q >= 0) {
       // P3[a][lF][si][rA] = sum_lA E[lA][a][lF] A[lA][si][rA]
-      for_2d(Aa * DlF * qi, DrA, [&](int row, int rA) {
-        const int si = row & (qi - 1), t = row >> lqi, a = t >= DlF ? 1 : 0, lF = t - a * DlF;
-        Real acc = 0;
-        for (int lA = 0; lA < DlA; ++lA) acc += E[(lA * Aa + a) * DlF + lF] * Aj[(lA * qi + si) * DrA + rA];
-        P3[row * DrA + rA] = acc;
-      });
+      contract_ea(E, Aj, P3, Aa, DlF, qi, DlA, DrA, lqi);
       __syncthreads();
       // G[a][si][so][b] = sum_{lF,rA} P3[a][lF][si][rA] P1r[lF][so][rA][b] / (sandwich value):
       // 8 lanes per entry split the (lF, rA) sum and add their parts in a fixed order
@@ -214,23 +246,31 @@ __device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
       }
       __syncthreads();
     }
-    // P2r[lF][si][a][rA] = sum_{so,b} P1r[lF][so][rA][b] W[a][si][so][b]
-    for_2d(DlF * qi * Aa, DrA, [&](int row, int rA) {
-      const int a = row & (Aa - 1), t = row >> lA_, si = t & (qi - 1), lF = t >> lqi;
+    // P2r[a][lF][si][rA] = sum_{so,b} P1r[lF][so][rA][b] W[a][si][so][b]
+    for_2d(Aa * DlF * qi, DrA, [&](int row, int rA) {
+      const int si = row & (qi - 1), t = row >> lqi, a = t >= DlF ? 1 : 0, lF = t - a * DlF;
       Real acc = 0;
       for (int so = 0; so < qo; ++so)
         for (int b = 0; b < B; ++b) acc += P1[((lF * qo + so) * DrA + rA) * B + b] * Wv[((a * qi + si) * qo + so) * B + b];
       P2[row * DrA + rA] = acc;
     });
     __syncthreads();
-    // Rn[lA][a][lF] = sum_{si,rA} A[lA][si][rA] P2r[lF][si][a][rA]
-    for_2d(DlA * Aa, DlF, [&](int row, int lF) {
-      const int a = row & (Aa - 1), lA = row >> lA_;
-      Real acc = 0;
-      for (int si = 0; si < qi; ++si)
-        for (int rA = 0; rA < DrA; ++rA) acc += Aj[(lA * qi + si) * DrA + rA] * P2[((lF * qi + si) * Aa + a) * DrA + rA];
-      Rn[row * DlF + lF] = acc;
-    });
+    // Rn[lA][a][lF] = sum_{si,rA} A[lA][si][rA] P2r[a][lF][si][rA]
+    if constexpr (MF) {
+      const int kq = qi * DrA;
+      gemm_mfma_f32(
+          Aa, DlA, DlF, kq, [&](int, int i, int k) { return (float)Aj[i * kq + k]; },
+          [&](int a, int k, int j) { return (float)P2[(a * DlF + j) * kq + k]; },
+          [&](int a, int i, int j, float v) { Rn[(i * Aa + a) * DlF + j] = Real(v); });
+    } else {
+      for_2d(DlA * Aa, DlF, [&](int row, int lF) {
+        const int a = row & (Aa - 1), lA = row >> lA_;
+        Real acc = 0;
+        for (int si = 0; si < qi; ++si)
+          for (int rA = 0; rA < DrA; ++rA) acc += Aj[(lA * qi + si) * DrA + rA] * P2[((a * DlF + lF) * qi + si) * DrA + rA];
+        Rn[row * DlF + lF] = acc;
+      });
+    }
     __syncthreads();
   }
   return true;

@@ -207,6 +207,36 @@ __device__ inline void gemm_mfma_bf16(int M, int N, int K, ALoad aload, BLoad bl
   }
 }
 
+// Batched FP32 GEMM on the matrix cores: for bt < nb, C_bt (M x N) = A_bt
+// (M x K) B_bt (K x N) with operands read through aload(bt, i, k) and
+// bload(bt, k, j), FP32 products accumulated in FP32 by v_mfma_f32_16x16x4_f32
+// (one 16x16 output tile per wave at a time, the tiles of every batch spread
+// over the waves).  Lane layout: A lane l holds row l%16, k = l/16; B lane l
+// holds column l%16, k = l/16; D lane l value i is row 4(l/16)+i, column l%16.
+template <typename ALoad, typename BLoad, typename Store>
+__device__ inline void gemm_mfma_f32(int nb, int M, int N, int K, ALoad aload, BLoad bload, Store store) {
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int tm = (M + 15) >> 4, tn = (N + 15) >> 4, per = tm * tn;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int t = wave; t < nb * per; t += NT / WAVE) {
+    const int bt = t / per, tt = t - bt * per;
+    const int i0 = (tt / tn) << 4, j0 = (tt % tn) << 4;
+    const int r = i0 + lr, c = j0 + lr;
+    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int kk = k0 + lk;
+      const float a = (r < M && kk < K) ? aload(bt, r, kk) : 0.f;
+      const float b = (kk < K && c < N) ? bload(bt, kk, c) : 0.f;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rr = i0 + lk * 4 + i;
+      if (rr < M && c < N) store(bt, rr, c, acc[i]);
+    }
+  }
+}
+
 // FP32 -> bf16 hi + lo (bits), the split of the three-product GEMMs.
 __device__ inline void split_bf16(float x, uint16_t& hi, uint16_t& lo) {
   const __bf16 h = (__bf16)x;

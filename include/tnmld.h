@@ -199,6 +199,17 @@ int tn_plan_info_rounds(int32_t d, int32_t chi, int32_t precision, int32_t round
  * or a tn_status. */
 int tn_plan_gemm_flops(int32_t d, int32_t chi, int32_t precision, double* out);
 
+/* HOST helper: counted work of tn_coset_loglik_backward for the plan of
+ * (d, chi, precision), with the same dense counts as tn_plan_info:
+ * out[0] the bottom-up sweep of one coset (transposed row MPOs from the last
+ * row up); out[1] the row environments of one coset (left and right
+ * environment steps along every row, and the derivative tensor of every site
+ * with a qubit); out[2] per syndrome as executed: the top sweep (rows common
+ * to the four cosets once) plus four bottom-up sweeps and four sets of row
+ * environments.  out: host array of >= 3 doubles.  Returns TN_OK or a
+ * tn_status. */
+int tn_plan_adjoint_flops(int32_t d, int32_t chi, int32_t precision, double* out);
+
 /* HOST helper: launch shape for (d, chi, precision) used by later calls in
  * this process: group = lattice columns per MPS site (1 or 2; 0 = automatic),
  * wg_per_cu = persistent work-groups per compute unit (1 or 2; 0 = as many as

@@ -64,6 +64,8 @@ def lib():
         L.tn_plan_info_rounds.argtypes = [I32, I32, I32, I32, ctypes.POINTER(D)]
         L.tn_plan_gemm_flops.restype = ctypes.c_int
         L.tn_plan_gemm_flops.argtypes = [I32, I32, I32, ctypes.POINTER(D)]
+        L.tn_plan_adjoint_flops.restype = ctypes.c_int
+        L.tn_plan_adjoint_flops.argtypes = [I32, I32, I32, ctypes.POINTER(D)]
         L.tn_set_tuning.restype = ctypes.c_int
         L.tn_set_tuning.argtypes = [I32, I32, I32, I32, I32]
         L.tn_set_tuning_ex.restype = ctypes.c_int

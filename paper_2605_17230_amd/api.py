@@ -415,11 +415,16 @@ def bitflip_plan_info(d):
 def plan_info(d, chi, precision="fp32", rounds=1):
     info = (ctypes.c_double * 8)()
     check_rc(lib().tn_plan_info_rounds(d, chi, PRECISIONS[precision], int(rounds), info))
-    gemm = (ctypes.c_double * 2)()
-    check_rc(lib().tn_plan_gemm_flops(d, chi, PRECISIONS[precision], gemm))
-    return dict(flops=info[0], scratch_bytes=info[1], lds_bytes=info[2], sites=int(info[3]),
-                rows=int(info[4]), group=int(info[5]), wg_per_cu=int(info[6]), flops_syndrome=info[7],
-                gemm_flops=gemm[0], gemm_flops_syndrome=gemm[1])
+    out = dict(flops=info[0], scratch_bytes=info[1], lds_bytes=info[2], sites=int(info[3]),
+               rows=int(info[4]), group=int(info[5]), wg_per_cu=int(info[6]), flops_syndrome=info[7])
+    if rounds <= 1:  # GEMM-class and adjoint counts of the one-round plan
+        gemm = (ctypes.c_double * 2)()
+        check_rc(lib().tn_plan_gemm_flops(d, chi, PRECISIONS[precision], gemm))
+        out.update(gemm_flops=gemm[0], gemm_flops_syndrome=gemm[1])
+        adj = (ctypes.c_double * 3)()
+        check_rc(lib().tn_plan_adjoint_flops(d, chi, PRECISIONS[precision], adj))
+        out.update(bottom_sweep_flops=adj[0], environment_flops=adj[1], adjoint_flops_syndrome=adj[2])
+    return out
 
 
 def set_tuning(d, chi, precision, group=0, wg_per_cu=0, threads=0):

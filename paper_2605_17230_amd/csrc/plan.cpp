@@ -51,6 +51,40 @@ inline double svd_flops(double M, double N) {  // dense SVD model 6 M N^2 + 20 N
   return 6.0 * M * N * N + 20.0 * N * N * N;
 }
 
+// Counted work of one site step of the implemented algorithm (standard dense
+// counts); *gemm gets its GEMM-class part.
+double site_flops(const SiteStep& S, double* gemm) {
+  const double m = S.m, nn = (double)S.qo * S.kr, rB = (double)S.Dr_old * S.B;
+  const double R = (double)S.Dl_new * S.qo, k2 = std::min(R, (double)S.kr);
+  double f = 2.0 * S.Dl_old * S.qi * S.Dr_old * S.A * S.qo * S.B;  // MPO apply
+  const double tl = 2.0 * m * S.qo * rB * S.kr;                      // (W A) . L
+  f += qr_flops(m, nn) + orgq_flops(nn, S.k);                        // LQ + explicit Q
+  const double cq = 2.0 * S.Dl_new * S.k * nn;                        // C . Q
+  f += qr_flops(R, S.kr) + orgq_flops(R, k2);                        // QR of the site matrix + Q
+  double qw = 0.0;
+  if (S.Dr_new < k2) {                                                // bond truncated:
+    f += svd_flops(S.kr, k2);                                         //   SVD of the R factor
+    qw = 2.0 * R * k2 * S.Dr_new;                                     //   A = Q W
+  }
+  *gemm = tl + cq + qw;
+  return f + tl + cq + qw;
+}
+
+// Counted work of the row environments at one site (adjoint): the left
+// environment step (three contractions), the right one (three) and, for a site
+// with a qubit, the derivative tensor (the top site with the left environment,
+// then the fold with the bottom side).  T: forward step of the row, Bv: the
+// bottom-up step whose input is the bottom MPS of that row.
+double env_flops(const SiteStep& T, const SiteStep& Bv) {
+  const double Aa = T.A, B = T.B, qi = T.qi, qo = T.qo, DlA = T.Dl_old, DrA = T.Dr_old, DlF = Bv.Dl_old,
+               DrF = Bv.Dr_old;
+  const double ea = 2.0 * Aa * DlF * qi * DrA * DlA;  // E . A
+  double f = ea + 2.0 * DlF * qo * B * DrA * Aa * qi + 2.0 * DrA * B * DrF * DlF * qo;   // left
+  f += 2.0 * DlF * qo * DrA * B * DrF + 2.0 * DlF * qi * Aa * DrA * qo * B + 2.0 * DlA * Aa * DlF * qi * DrA;  // right
+  if (T.q >= 0) f += ea + 2.0 * Aa * qi * qo * B * DlF * DrA;  // derivative tensor
+  return f;
+}
+
 }  // namespace
 
 std::string build_plan(int d, int chi, int group, Plan* out, int rounds) {
@@ -269,21 +303,9 @@ std::string build_plan(int d, int chi, int group, Plan* out, int rounds) {
       h.max_m = std::max(h.max_m, (int)S.m);
       h.max_rows = std::max(h.max_rows, S.Dl_new * S.qo);
       h.max_bond = std::max({h.max_bond, (int)S.Dl_new, (int)S.Dr_new, (int)S.Dl_old, (int)S.Dr_old});
-      // counted work of the implemented algorithm (standard dense counts):
-      double m = S.m, nn = (double)S.qo * S.kr;
-      double R = (double)S.Dl_new * S.qo, k2 = std::min(R, (double)S.kr);
-      flops += 2.0 * S.Dl_old * S.qi * S.Dr_old * S.A * S.qo * S.B;  // MPO apply
-      const double tl = 2.0 * m * S.qo * rB * S.kr;                     // (W A) . L
-      flops += qr_flops(m, nn) + orgq_flops(nn, S.k);                  // LQ + explicit Q
-      const double cq = 2.0 * S.Dl_new * S.k * nn;                      // C . Q
-      flops += qr_flops(R, S.kr) + orgq_flops(R, k2);                  // QR of the site matrix + Q
-      double qw = 0.0;
-      if (S.Dr_new < k2) {                                              // bond truncated:
-        flops += svd_flops(S.kr, k2);                                   //   SVD of the R factor
-        qw = 2.0 * R * k2 * S.Dr_new;                                   //   A = Q W
-      }
-      flops += tl + cq + qw;
-      gemm += tl + cq + qw;
+      double g = 0.0;
+      flops += site_flops(S, &g);
+      gemm += g;
     }
     if (u + 1 == h.shared_rows) {
       h.flops_shared = flops;
@@ -381,6 +403,17 @@ std::string build_plan(int d, int chi, int group, Plan* out, int rounds) {
     }
     env_max = std::max(env_max, env);
   }
+  // adjoint work per coset: the bottom-up sweep and the row environments
+  h.flops_bu = 0.0;
+  h.flops_env = 0.0;
+  for (int s2 = 0; s2 < nstep; ++s2)
+    for (int J = 0; J < nsite; ++J) {
+      double g = 0.0;
+      h.flops_bu += site_flops(bu[(size_t)s2 * nsite + J], &g);
+    }
+  for (int u = 0; u < nstep; ++u)
+    for (int J = 0; J < nsite; ++J)
+      h.flops_env += env_flops(steps[(size_t)u * nsite + J], bu[(size_t)(nstep - 1 - u) * nsite + J]);
   int64_t tmp_max = 64;
   for (int u = 0; u < nstep; ++u)
     for (int J = 0; J < nsite; ++J) {

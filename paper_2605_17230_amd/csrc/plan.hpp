@@ -112,6 +112,8 @@ struct PlanHeader {  // device-visible, followed by the tables at the offsets be
   double flops_shared;  // the part of flops_fwd spent in rows 0..shared_rows-1
   double flops_gemm;         // GEMM-class part of flops_fwd (T.L, C.Q, and Q.W on truncated bonds)
   double flops_gemm_shared;  // the part of flops_gemm spent in rows 0..shared_rows-1
+  double flops_bu;           // counted flops of one coset's bottom-up sweep (adjoint), as flops_fwd
+  double flops_env;          // counted flops of one coset's row environments and derivative tensors (adjoint)
 };
 
 struct Plan {

@@ -860,6 +860,17 @@ int tn_code_stabilizers(int32_t d, int32_t* type_out, int32_t* support_out) {
   return j;
 }
 
+int tn_plan_adjoint_flops(int32_t d, int32_t chi, int32_t precision, double* out) {
+  if (!out || precision < TN_FP64 || precision > TN_FP32_PLAIN) return fail(TN_EINVAL, "bad arguments");
+  Plan p;
+  std::string why;
+  if (choose_group(d, chi, precision, kLdsLimit, &p, &why) < 0) return fail(TN_EUNSUPPORTED, why);
+  out[0] = p.h.flops_bu;
+  out[1] = p.h.flops_env;
+  out[2] = p.h.flops_shared + 4.0 * (p.h.flops_fwd - p.h.flops_shared) + 4.0 * (p.h.flops_bu + p.h.flops_env);
+  return TN_OK;
+}
+
 int tn_plan_gemm_flops(int32_t d, int32_t chi, int32_t precision, double* out) {
   if (!out || precision < TN_FP64 || precision > TN_FP32_PLAIN) return fail(TN_EINVAL, "bad arguments");
   Plan p;

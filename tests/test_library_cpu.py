@@ -212,3 +212,17 @@ def test_gradient_rejects_repeated_rounds(L):
     g = (ctypes.c_void_p * 1)(1)
     rc = L.tn_coset_loglik_backward(arr, 1, g, g, 0, None, 0, None)
     assert rc == _lib.TN_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("d,chi", [(5, 8), (11, 24), (17, 32)])
+def test_adjoint_flop_counts(d, chi):
+    """tn_plan_adjoint_flops: the bottom-up sweep of a coset mirrors the
+    top-down one on the 180-degree symmetric patch (same count within 10 %),
+    the row environments add work, and the per-syndrome total is the top sweep
+    as executed plus four bottom sweeps and four sets of environments."""
+    import paper_2605_17230_amd as tn
+    i = tn.plan_info(d, chi, "fp32")
+    assert 0.9 < i["bottom_sweep_flops"] / i["flops"] < 1.1
+    assert 0 < i["environment_flops"] < i["flops"]
+    tot = i["flops_syndrome"] + 4.0 * (i["bottom_sweep_flops"] + i["environment_flops"])
+    assert abs(i["adjoint_flops_syndrome"] - tot) <= 1e-9 * tot

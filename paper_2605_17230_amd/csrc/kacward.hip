@@ -108,6 +108,7 @@ __device__ void kw_item(const Job& job, int64_t b, int coset, double2* A, unsign
   __shared__ uint8_t s_f[TN_MAX_D * TN_MAX_D];
   __shared__ double2 s_prow[NB];
   __shared__ double2 s_L[NB][NB];
+  __shared__ double2 s_Li[NB][NB];
   __shared__ int s_ipiv[NB];
   __shared__ double s_rv[NT / WAVE];
   __shared__ int s_ri[NT / WAVE];
@@ -237,38 +238,66 @@ __device__ void kw_item(const Job& job, int64_t b, int coset, double2* A, unsign
       __syncthreads();
     }
     if (singular || k1 >= N) break;
-    // rows k0..k1-1 of the trailing columns: the panel's row swaps, then the
-    // unit-lower solve with L11 (one thread per column)
-    for (int e = tid; e < kb * kb; e += NT) {
-      const int r = e / kb, c = e % kb;
-      s_L[r][c] = A[(int64_t)(k0 + r) * ld + k0 + c];
-    }
-    __syncthreads();
-    for (int c = k1 + tid; c < N; c += NT) {
-      double2 u[NB];
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj) {
-        if (jj < kb) {
-          const int r = k0 + jj, pr = s_ipiv[jj];
-          double2 x = A[(int64_t)r * ld + c];
-          if (pr != r) {
-            const double2 y = A[(int64_t)pr * ld + c];
-            A[(int64_t)pr * ld + c] = x;
-            x = y;
-          }
-          u[jj] = x;
+    // rows k0..k1-1 of the trailing columns: the panel's row swaps (thread per
+    // column, in pivot order), then U12 = L11^-1 A12 with the inverse of the
+    // unit-lower L11 formed in LDS and applied on the matrix cores
+    for (int c = k1 + tid; c < N; c += NT)
+      for (int jj = 0; jj < kb; ++jj) {
+        const int r = k0 + jj, pr = s_ipiv[jj];
+        if (pr != r) {
+          const double2 x = A[(int64_t)r * ld + c];
+          A[(int64_t)r * ld + c] = A[(int64_t)pr * ld + c];
+          A[(int64_t)pr * ld + c] = x;
         }
       }
+    for (int e = tid; e < NB * NB; e += NT) {
+      const int r = e / NB, c = e % NB;
+      s_L[r][c] = (r < kb && c < kb) ? A[(int64_t)(k0 + r) * ld + k0 + c] : make_double2(0.0, 0.0);
+      s_Li[r][c] = make_double2(r == c && r < kb ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    if (tid < kb) {  // column j of L11^-1 by forward substitution, in LDS
+      const int j = tid;
+      for (int i = j + 1; i < kb; ++i) {
+        double2 acc = s_L[i][j];
+        for (int mm = j + 1; mm < i; ++mm) {
+          const double2 l = s_L[i][mm], x = s_Li[mm][j];
+          acc = make_double2(acc.x + (l.x * x.x - l.y * x.y), acc.y + (l.x * x.y + l.y * x.x));
+        }
+        s_Li[i][j] = make_double2(-acc.x, -acc.y);
+      }
+    }
+    __syncthreads();
+    const int lane = tid % WAVE, wv = tid / WAVE;
+    const int nks = kb >> 2;  // k-steps of 4 (kb is a multiple of 4: N = 2(d^2 + 1) and NB are)
+    {
+      // one wave per block of 16 columns: its kb rows are read into registers
+      // before either 16-row half of the product is written back in place
+      const int nct = (ld - k1) / 16;
+      for (int cb = wv; cb < nct; cb += NT / WAVE) {
+        const int c0 = k1 + 16 * cb;
+        double2 bq[NB / 4];
 #pragma unroll
-      for (int jj = 0; jj < NB; ++jj) {
-        if (jj < kb) {
+        for (int s2 = 0; s2 < NB / 4; ++s2)
+          if (s2 < nks) bq[s2] = A[(int64_t)(k0 + 4 * s2 + lane / 16) * ld + c0 + lane % 16];
 #pragma unroll
-          for (int ii = 0; ii < NB; ++ii)
-            if (ii > jj && ii < kb) {
-              const double2 l = s_L[ii][jj];
-              u[ii] = make_double2(u[ii].x - (l.x * u[jj].x - l.y * u[jj].y), u[ii].y - (l.x * u[jj].y + l.y * u[jj].x));
+        for (int h = 0; h < NB / 16; ++h) {
+          if (16 * h >= kb) break;
+          f64x4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int s2 = 0; s2 < NB / 4; ++s2)
+            if (s2 < nks) {
+              const double2 a = s_Li[16 * h + lane % 16][4 * s2 + lane / 16], bb = bq[s2];
+              cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bb.x, cr, 0, 0, 0);
+              cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, bb.y, cr, 0, 0, 0);
+              ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bb.y, ci, 0, 0, 0);
+              ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, bb.x, ci, 0, 0, 0);
             }
-          A[(int64_t)(k0 + jj) * ld + c] = u[jj];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * h + lane / 16 + 4 * v;
+            if (r < kb) A[(int64_t)(k0 + r) * ld + c0 + lane % 16] = make_double2(cr[v], ci[v]);
+          }
         }
       }
     }
@@ -276,12 +305,21 @@ __device__ void kw_item(const Job& job, int64_t b, int coset, double2* A, unsign
     // trailing update A[k1:, k1:] -= A[k1:, k0:k1] A[k0:k1, k1:] on the matrix cores:
     // 16 x 16 complex tiles; v_mfma_f64_16x16x4_f64 takes A[l % 16][l / 16] and
     // B[l / 16][l % 16] from lane l and leaves D[l / 16 + 4 v][l % 16] in its v-th value
-    const int lane = tid % WAVE, wv = tid / WAVE;
     const int nt = (ld - k1) / 16;
     bv = -1.0;
     bi = -1;
     for (int t = wv; t < nt * nt; t += NT / WAVE) {
       const int i0 = k1 + 16 * (t / nt), c0 = k1 + 16 * (t % nt);
+      // every operand of the tile is loaded before the matrix-core chain, so
+      // the loads overlap instead of waiting one k-step at a time
+      double2 av[NB / 4], bv2[NB / 4];
+#pragma unroll
+      for (int s = 0; s < NB / 4; ++s)
+        if (s < nks) {
+          const int ks = k0 + 4 * s;
+          av[s] = A[(int64_t)(i0 + lane % 16) * ld + ks + lane / 16];
+          bv2[s] = A[(int64_t)(ks + lane / 16) * ld + c0 + lane % 16];
+        }
       f64x4 cr, ci;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -289,14 +327,15 @@ __device__ void kw_item(const Job& job, int64_t b, int coset, double2* A, unsign
         cr[v] = x.x;
         ci[v] = x.y;
       }
-      for (int ks = k0; ks < k1; ks += 4) {
-        const double2 a = A[(int64_t)(i0 + lane % 16) * ld + ks + lane / 16];
-        const double2 bb = A[(int64_t)(ks + lane / 16) * ld + c0 + lane % 16];
-        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, bb.x, cr, 0, 0, 0);
-        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, bb.y, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, bb.y, ci, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, bb.x, ci, 0, 0, 0);
-      }
+#pragma unroll
+      for (int s = 0; s < NB / 4; ++s)
+        if (s < nks) {
+          const double2 a = av[s], bb = bv2[s];
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, bb.x, cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, bb.y, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, bb.y, ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, bb.x, ci, 0, 0, 0);
+        }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = i0 + lane / 16 + 4 * v;

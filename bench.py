@@ -121,6 +121,17 @@ def cpu_baseline(d, rates, syn, target_s, min_count=256):
 DTYPE = {"fp32plain": "f32", "fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32"}
 
 
+def max_finite_diff(a, b):
+    """Largest |a - b| over the cosets finite in both (lists of [B, 4] arrays);
+    cosets -inf in one form only are counted separately by the caller."""
+    m = 0.0
+    for x, y in zip(a, b):
+        both = np.isfinite(x) & np.isfinite(y)
+        if both.any():
+            m = max(m, float(np.max(np.abs(x[both] - y[both]))))
+    return m
+
+
 def kernel_sources_sha256():
     import glob
     import hashlib
@@ -570,8 +581,9 @@ def main():
         ms2 = e0.elapsed_time(e1)
         out["compare"] = {"precision": a.compare, "value": n_syn / (ms2 / 1e3), "ms_per_step": ms2,
                           "speedup_of_primary": ms2 / ms_step,
-                          "max_abs_dlogz_vs_primary": float(max(np.max(np.abs(x.logz.cpu().numpy() - y))
-                                                                for x, y in zip(o2, lz))),
+                          "max_abs_dlogz_vs_primary": max_finite_diff([x.logz.cpu().numpy() for x in o2], lz),
+                          "cosets_finite_in_one_form_only": int(sum(
+                              int((np.isfinite(x.logz.cpu().numpy()) != np.isfinite(y)).sum()) for x, y in zip(o2, lz))),
                           "class_agreement_with_primary": float(np.mean(np.concatenate(
                               [x.cls.cpu().numpy() == y for x, y in zip(o2, cls)])))}
         print("bench: compare %s %.1f ms" % (a.compare, ms2), file=sys.stderr, flush=True)

@@ -132,11 +132,19 @@ def max_finite_diff(a, b):
     return m
 
 
+# Sources the boundary-MPS kernels (fwd_kernel, its 256-thread build, bwd_kernel)
+# are compiled from; the planar solver's files are not among them.
+FWD_SOURCES = ("adjoint.hpp", "contract.hpp", "plan.cpp", "plan.hpp", "sweep.hpp", "tnmld.hip", "tnmld_small.hip")
+
+
 def kernel_sources_sha256():
-    import glob
+    """sha256 over the names and contents of the boundary-MPS kernel sources
+    and the C header, in sorted order."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2605_17230_amd", "csrc", "*"))):
+    files = [os.path.join(ROOT, "paper_2605_17230_amd", "csrc", f) for f in FWD_SOURCES]
+    files.append(os.path.join(ROOT, "include", "tnmld.h"))
+    for f in sorted(files, key=os.path.basename):
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())

@@ -170,6 +170,33 @@ int tn_coset_loglik_backward(const tn_segment* segs, int32_t nseg, const double*
                              double* const* grad_log_rates, int32_t forward_done, void* workspace, size_t ws_bytes,
                              void* stream);
 
+/* The same gradient in two calls, for callers that need log P(s) before they
+ * know grad_logp (a training step: loss first, gradient after).  The top
+ * sweep's states (the boundary MPS before every row of every coset, the rows
+ * common to the cosets once per syndrome) are kept in caller memory between
+ * the calls instead of recomputed, trading device memory (tn_states_size
+ * bytes, e.g. about 2.9 MB per syndrome at d = 11, chi = 24 in FP32) for the
+ * top sweep of the second call (eq. "dmle_loss", Sec. 3.2.4).
+ *
+ * tn_states_size: bytes of that buffer for these segments (0 on invalid
+ * arguments; every segment one round).
+ * tn_coset_loglik_save: writes out_logz and out_logp (required) as
+ * tn_coset_loglik does, and the states into `states` (device, caller-owned,
+ * states_bytes >= tn_states_size); workspace as for the backward.
+ * tn_coset_loglik_backward_saved: accumulates (+=) the gradient into
+ * grad_log_rates (as tn_coset_loglik_backward) from the states and from the
+ * out_logz / out_logp that tn_coset_loglik_save wrote for exactly the same
+ * segments and values (the segment array may be a copy; the buffers it points
+ * to must be unchanged).  Results equal tn_coset_loglik_backward's bit for bit.
+ * Errors as tn_coset_loglik_backward; a states buffer that is NULL or too small
+ * is TN_EINVAL. */
+size_t tn_states_size(const tn_segment* segs, int32_t nseg);
+int tn_coset_loglik_save(const tn_segment* segs, int32_t nseg, void* states, size_t states_bytes, void* workspace,
+                         size_t ws_bytes, void* stream);
+int tn_coset_loglik_backward_saved(const tn_segment* segs, int32_t nseg, const double* const* grad_logp,
+                                   double* const* grad_log_rates, const void* states, size_t states_bytes,
+                                   void* workspace, size_t ws_bytes, void* stream);
+
 /* HOST helper: check layout of distance d.  type_out: host [d*d-1] (0 = X-type,
  * 1 = Z-type); support_out: host [d*d-1][4] qubit indices, -1 padded.
  * Returns d*d-1, or TN_EINVAL. */

@@ -5,8 +5,8 @@ marshals arguments.  See include/tnmld.h for the C ABI.
 """
 from ._lib import TNError, lib, LIB_PATH  # noqa: F401
 from .api import (SegmentInput, SegmentOutput, bitflip_plan_info, check_input_values, code_stabilizers,  # noqa: F401
-                  coset_loglik, coset_loglik_backward, decode, decode_bitflip, decode_bitflip_segments, decode_segments,
-                  decode_rounds, log_posterior, plan_info, set_tuning, workspace_bytes)
+                  coset_loglik, coset_loglik_backward, coset_loglik_backward_saved, coset_loglik_save, decode, decode_bitflip, decode_bitflip_segments, decode_segments,
+                  decode_rounds, log_posterior, plan_info, set_tuning, states_bytes, workspace_bytes)
 from .fit import fit_log_rates  # noqa: F401
 
 from . import tune as _tune  # noqa: E402

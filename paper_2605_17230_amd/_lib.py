@@ -64,6 +64,12 @@ def lib():
         L.tn_plan_info_rounds.argtypes = [I32, I32, I32, I32, ctypes.POINTER(D)]
         L.tn_plan_gemm_flops.restype = ctypes.c_int
         L.tn_plan_gemm_flops.argtypes = [I32, I32, I32, ctypes.POINTER(D)]
+        L.tn_states_size.restype = SZ
+        L.tn_states_size.argtypes = [seg_p, I32]
+        L.tn_coset_loglik_save.restype = ctypes.c_int
+        L.tn_coset_loglik_save.argtypes = [seg_p, I32, P, SZ, P, SZ, P]
+        L.tn_coset_loglik_backward_saved.restype = ctypes.c_int
+        L.tn_coset_loglik_backward_saved.argtypes = [seg_p, I32, ctypes.POINTER(P), ctypes.POINTER(P), P, SZ, P, SZ, P]
         L.tn_plan_adjoint_flops.restype = ctypes.c_int
         L.tn_plan_adjoint_flops.argtypes = [I32, I32, I32, ctypes.POINTER(D)]
         L.tn_set_tuning.restype = ctypes.c_int

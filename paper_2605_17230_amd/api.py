@@ -327,15 +327,106 @@ def coset_loglik_backward(segs, grad_logp, stream=None, outputs=None, workspace_
     return outs, grads
 
 
+def states_bytes(segs):
+    """Device bytes of the top-sweep states that coset_loglik_save keeps for
+    coset_loglik_backward_saved (the MPS before every row of every coset, the
+    rows common to the cosets once per syndrome)."""
+    arr, _, _ = _prepare(segs, check=False)
+    return int(lib().tn_states_size(arr, len(segs)))
+
+
+def coset_loglik_save(segs, stream=None, workspace_buf=None, check: bool = True, states=None):
+    """First call of the two-call gradient: log Z / log P(s) of every segment
+    (as coset_loglik) and the top sweep's states, kept in a device buffer for
+    coset_loglik_backward_saved, which then runs only the bottom sweeps.
+    Returns (outputs, states).  states: optional caller-owned uint8 device
+    tensor of at least states_bytes(segs) bytes."""
+    capturing = torch.cuda.is_current_stream_capturing()
+    do_check = bool(check) and not capturing
+    arr, outs, keep = _prepare(segs, do_check and check != "device")
+    L = lib()
+    nbytes = L.tn_workspace_size(arr, len(segs), 1)
+    sbytes = L.tn_states_size(arr, len(segs))
+    if nbytes == 0 or sbytes == 0:
+        check_rc(_lib.TN_EINVAL if not L.tn_last_error() else -1)
+    dev = segs[0].syndromes.device
+    ws = _pick_workspace(workspace_buf, nbytes, dev, stream)
+    if states is None:
+        states = torch.empty(sbytes, dtype=torch.uint8, device=dev)
+    elif states.dtype != torch.uint8 or not states.is_cuda or states.numel() < sbytes:
+        raise ValueError("states must be a uint8 device tensor of at least %d bytes" % sbytes)
+    st = _launch_stream(stream, dev, keep + [states], outs)
+    check_rc(L.tn_coset_loglik_save(arr, len(segs), ctypes.c_void_p(states.data_ptr()), states.numel(),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(st)))
+    if do_check:
+        _check_status(ws, st)
+    del keep
+    return outs, states
+
+
+def coset_loglik_backward_saved(segs, grad_logp, outputs, states, stream=None, workspace_buf=None, check=True):
+    """Second call of the two-call gradient: d (sum_b grad_logp[b] log P(s_b))
+    / d ln rates from the outputs and states of coset_loglik_save on exactly
+    these inputs (the bottom sweeps and row environments only).  Returns grads
+    as coset_loglik_backward."""
+    if any((s.rounds or 1) > 1 for s in segs):
+        raise ValueError("the gradient takes segments of one syndrome round")
+    arr, outs, keep = _prepare(segs, False)
+    if len(outputs) != len(segs):
+        raise ValueError("one output per segment")
+    for i, o in enumerate(outputs):
+        if o.logz.shape != outs[i].logz.shape or o.logp.shape != outs[i].logp.shape:
+            raise ValueError("outputs do not match the segments")
+        arr[i].out_logz = o.logz.data_ptr()
+        arr[i].out_logp = o.logp.data_ptr()
+        arr[i].out_class = o.cls.data_ptr()
+    L = lib()
+    nbytes = L.tn_workspace_size(arr, len(segs), 1)
+    if nbytes == 0:
+        check_rc(_lib.TN_EINVAL if not L.tn_last_error() else -1)
+    dev = segs[0].syndromes.device
+    ws = _pick_workspace(workspace_buf, nbytes, dev, stream)
+    gp = [g.to(device=dev, dtype=torch.float64).contiguous() for g in grad_logp]
+    grads = []
+    for s, g in zip(segs, gp):
+        m = s.rates.shape[0] if s.rates.dim() == 3 else 1
+        if g.shape != (s.syndromes.shape[0],):
+            raise ValueError("grad_logp[i] must be [B]")
+        grads.append(torch.zeros((m, s.d * s.d, 3), dtype=torch.float64, device=dev))
+    gp_arr = (ctypes.c_void_p * len(segs))(*[g.data_ptr() for g in gp])
+    gr_arr = (ctypes.c_void_p * len(segs))(*[g.data_ptr() for g in grads])
+    st = _launch_stream(stream, dev, keep + gp + grads + [states], list(outputs))
+    check_rc(L.tn_coset_loglik_backward_saved(arr, len(segs), gp_arr, gr_arr, ctypes.c_void_p(states.data_ptr()),
+                                              states.numel(), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                              ctypes.c_void_p(st)))
+    do_check = bool(check) and not torch.cuda.is_current_stream_capturing()
+    if do_check:
+        _check_status(ws, st)
+    del keep
+    return grads
+
+
+# Largest top-sweep state buffer the autograd binding keeps between its
+# forward and backward; above it the backward recomputes the top sweep.
+STATES_LIMIT_BYTES = 32 << 30
+
+
 class _LogPosterior(torch.autograd.Function):
     """log P(s_b) as a function of theta = ln rates; the backward is the
-    library's adjoint contraction."""
+    library's adjoint contraction.  The forward keeps the top sweep's states
+    (when they fit STATES_LIMIT_BYTES), so the backward runs only the bottom
+    sweeps."""
 
     @staticmethod
     def forward(ctx, log_rates, syndromes, model_index, d, chi, precision):
         rates = log_rates.detach().exp()
         seg = SegmentInput(d, chi, syndromes, rates, model_index, precision)
-        o = decode_segments([seg])[0]
+        ctx.states = None
+        if states_bytes([seg]) <= STATES_LIMIT_BYTES:
+            outs, ctx.states = coset_loglik_save([seg])
+            o = outs[0]
+        else:
+            o = decode_segments([seg])[0]
         ctx.seg = seg
         ctx.out = o
         ctx.rates_dim = log_rates.dim()
@@ -346,7 +437,11 @@ class _LogPosterior(torch.autograd.Function):
     def backward(ctx, g_logp, g_logz):
         if g_logz is not None and bool((g_logz != 0).any()):
             raise NotImplementedError("only log P(s) is differentiable")
-        _, grads = coset_loglik_backward([ctx.seg], [g_logp], outputs=[ctx.out])
+        if ctx.states is not None:
+            grads = coset_loglik_backward_saved([ctx.seg], [g_logp], [ctx.out], ctx.states)
+            ctx.states = None
+        else:
+            _, grads = coset_loglik_backward([ctx.seg], [g_logp], outputs=[ctx.out])
         g = grads[0] if ctx.rates_dim == 3 else grads[0][0]
         return g, None, None, None, None, None
 

@@ -286,10 +286,15 @@ __device__ bool row_gradient(const SiteStep* frow, const SiteStep* brow, int nsi
 // elements): top regions | bottom regions | stored states (the shared rows
 // once, then nstep - S per coset; mps_elems each) | environments | three
 // temporaries.  write_fwd: also write log Z and log P(s) of the item.
+// mode: ADJ_FUSED both sweeps in this call; ADJ_TOP the top sweep only,
+// its states stored in job.states (the caller's memory, states_stride
+// elements per syndrome) and log Z / log P(s) written; ADJ_BOTTOM the bottom
+// sweeps only, against the states and log Z / log P(s) an ADJ_TOP call left.
 // Collective.
+enum { ADJ_FUSED = 0, ADJ_TOP = 1, ADJ_BOTTOM = 2 };
 template <typename Real, typename Fac, int GM>
 __device__ void adjoint_syndrome(const JobDev& job, int64_t b, uint8_t* smem, const LdsLayout& lay, Real* scr,
-                                 int write_fwd, double* part) {
+                                 int write_fwd, double* part, int mode = ADJ_FUSED) {
   const uint8_t* plan = job.plan;
   const PlanHeader* H = reinterpret_cast<const PlanHeader*>(plan);
   const int n = H->n, m = H->m, nsite = H->nsite, nstep = H->nstep;
@@ -319,8 +324,8 @@ __device__ void adjoint_syndrome(const JobDev& job, int64_t b, uint8_t* smem, co
   const int64_t se = H->scratch_elems, me = H->mps_elems;
   Real* top = scr;
   Real* bot = scr + se;
-  Real* states = scr + 2 * se;
-  Real* env = states + (int64_t)(S + 4 * (nstep - S)) * me;
+  Real* env = scr + 2 * se + (int64_t)(S + 4 * (nstep - S)) * me;
+  Real* states = mode == ADJ_FUSED ? scr + 2 * se : reinterpret_cast<Real*>(job.states) + b * job.states_stride;
   Real* P1 = env + H->env_elems;
   Real* P2 = P1 + H->tmp_elems;
   Real* P3 = P2 + H->tmp_elems;
@@ -334,36 +339,48 @@ __device__ void adjoint_syndrome(const JobDev& job, int64_t b, uint8_t* smem, co
       Dr = row[J].Dr_old;
     };
   };
-  // --- top-down: the shared rows once (the reference error of any coset
-  // agrees on them), then each coset, storing the state before every row ---
-  prep_reference(H, checks, syn, 0, w.syn, w.fbits, &s_label);
-  mps_ones(top, region, plan + H->init_qi_ofs, nsite);
-  double base = 0.0;
-  bool alive = true;
-  for (int u = 0; u < S && alive; ++u) {
-    const SiteStep* row = steps + (int64_t)u * nsite;
-    mps_pack(top, region, nsite, in_dims(row), state_of(0, u), false, top);
-    alive = row_step_outlined<Real, Fac, GM>(row, nsite, codes, rates, top, region, w, base);
-  }
   int dead = 0;  // thread 0: cosets with Z = 0
-  for (int mlog = 0; mlog < 4; ++mlog) {
-    const int label = prep_reference(H, checks, syn, mlog, w.syn, w.fbits, &s_label);
-    double logscale = base;
-    bool ok = alive;
-    if (ok && mlog > 0 && S < nstep)  // restart from the state after the shared rows
-      mps_pack(top, region, nsite, in_dims(steps + (int64_t)S * nsite), state_of(0, S), true, top);
-    for (int u = S; u < nstep && ok; ++u) {
+  if (mode != ADJ_BOTTOM) {
+    // --- top-down: the shared rows once (the reference error of any coset
+    // agrees on them), then each coset, storing the state before every row ---
+    prep_reference(H, checks, syn, 0, w.syn, w.fbits, &s_label);
+    mps_ones(top, region, plan + H->init_qi_ofs, nsite);
+    double base = 0.0;
+    bool alive = true;
+    for (int u = 0; u < S && alive; ++u) {
       const SiteStep* row = steps + (int64_t)u * nsite;
-      mps_pack(top, region, nsite, in_dims(row), state_of(mlog, u), false, top);
-      ok = row_step_outlined<Real, Fac, GM>(row, nsite, codes, rates, top, region, w, logscale);
+      mps_pack(top, region, nsite, in_dims(row), state_of(0, u), false, top);
+      alive = row_step_outlined<Real, Fac, GM>(row, nsite, codes, rates, top, region, w, base);
     }
-    const double lz = finish_logz(ok ? logscale + mps_close<Real, Fac>(top, region, fin, nsite, w.sig) : -INFINITY);
-    if (threadIdx.x == 0) {
-      s_lz[mlog] = lz;
-      s_lab[mlog] = label;
-      dead += lz == -INFINITY;
+    for (int mlog = 0; mlog < 4; ++mlog) {
+      const int label = prep_reference(H, checks, syn, mlog, w.syn, w.fbits, &s_label);
+      double logscale = base;
+      bool ok = alive;
+      if (ok && mlog > 0 && S < nstep)  // restart from the state after the shared rows
+        mps_pack(top, region, nsite, in_dims(steps + (int64_t)S * nsite), state_of(0, S), true, top);
+      for (int u = S; u < nstep && ok; ++u) {
+        const SiteStep* row = steps + (int64_t)u * nsite;
+        mps_pack(top, region, nsite, in_dims(row), state_of(mlog, u), false, top);
+        ok = row_step_outlined<Real, Fac, GM>(row, nsite, codes, rates, top, region, w, logscale);
+      }
+      const double lz = finish_logz(ok ? logscale + mps_close<Real, Fac>(top, region, fin, nsite, w.sig) : -INFINITY);
+      if (threadIdx.x == 0) {
+        s_lz[mlog] = lz;
+        s_lab[mlog] = label;
+        dead += lz == -INFINITY;
+      }
+      __syncthreads();
     }
-    __syncthreads();
+  } else {
+    // log Z of the cosets from the call that stored the states
+    for (int mlog = 0; mlog < 4; ++mlog) {
+      const int label = prep_reference(H, checks, syn, mlog, w.syn, w.fbits, &s_label);
+      if (threadIdx.x == 0) {
+        s_lz[mlog] = job.logz[b * 4 + label];
+        s_lab[mlog] = label;
+      }
+      __syncthreads();
+    }
   }
   if (threadIdx.x == 0) {
     double mx = -INFINITY;
@@ -374,7 +391,7 @@ __device__ void adjoint_syndrome(const JobDev& job, int64_t b, uint8_t* smem, co
       for (int k = 0; k < 4; ++k) sum += exp(s_lz[k] - mx);
       lp = mx + log(sum);
     }
-    const double gp = job.gradp[b];
+    const double gp = mode == ADJ_TOP ? 0.0 : job.gradp[b];
     for (int k = 0; k < 4; ++k)
       s_weight[k] = (s_lz[k] > -INFINITY && lp > -INFINITY && gp != 0.0) ? gp * exp(s_lz[k] - lp) : 0.0;
     if (write_fwd) {
@@ -384,6 +401,7 @@ __device__ void adjoint_syndrome(const JobDev& job, int64_t b, uint8_t* smem, co
     }
   }
   __syncthreads();
+  if (mode == ADJ_TOP) return;
   double* pm = part + (int64_t)model * n * 3;
   // --- bottom-up per coset, against the stored top states ------------------
   for (int mlog = 0; mlog < 4; ++mlog) {

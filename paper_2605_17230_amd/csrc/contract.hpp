@@ -29,6 +29,8 @@ struct JobDev {
   int32_t rounds;       // syndrome rounds per item (0 or 1: one perfect round)
   unsigned* status;     // status word of the call (ST_* bits), in the workspace header
   const double* meas;   // repeated rounds: [n_models][m] measurement flip probabilities
+  void* states;         // backward in two calls: this job's top-sweep states (caller memory), or null
+  int64_t states_stride;  // elements of one syndrome's states
 };
 
 struct JobTable {

@@ -44,7 +44,7 @@ int launch_fwd_small(int precision, const void* jt, unsigned long long* counter,
                      int64_t snap_ofs, const void* lay, int lds_bytes, int nwg, hipStream_t st);
 int small_bwd_wgs_per_cu(int precision, int lds_bytes);
 int launch_bwd_small(int precision, const void* jt, char* scratch, int64_t stride, const void* lay, int lds_bytes,
-                     int write_fwd, double* partials, int64_t pstride, int nwg, hipStream_t st);
+                     int flags, double* partials, int64_t pstride, int nwg, hipStream_t st);
 }  // namespace tnmld_small
 
 namespace tnmld {
@@ -76,8 +76,9 @@ __global__ __launch_bounds__(NT) void fwd_kernel(JobTable jt, unsigned long long
 // Backward: each work-group walks a fixed stride of items (deterministic order)
 // and accumulates into its own FP64 partial gradient.
 template <typename Real, typename Fac, int GM>
+// flags: bit 0 writes log Z and log P(s); bits 1-2 the ADJ_* mode.
 __global__ __launch_bounds__(NT) void bwd_kernel(JobTable jt, char* scratch, int64_t scratch_stride, LdsLayout lay,
-                                                  int write_fwd, double* partials, int64_t part_stride) {
+                                                  int flags, double* partials, int64_t part_stride) {
   extern __shared__ __align__(16) uint8_t smem[];
   Real* scr = reinterpret_cast<Real*>(scratch + (int64_t)blockIdx.x * scratch_stride);
   double* mypart = partials + (int64_t)blockIdx.x * part_stride;
@@ -85,7 +86,8 @@ __global__ __launch_bounds__(NT) void bwd_kernel(JobTable jt, char* scratch, int
     int jb = 0;
     while (jb + 1 < jt.n && jt.j[jb + 1].item_begin <= item) ++jb;
     const JobDev& job = jt.j[jb];
-    adjoint_syndrome<Real, Fac, GM>(job, item - job.item_begin, smem, lay, scr, write_fwd, mypart + job.part_ofs);
+    adjoint_syndrome<Real, Fac, GM>(job, item - job.item_begin, smem, lay, scr, flags & 1, mypart + job.part_ofs,
+                                    flags >> 1);
     __syncthreads();
   }
 }
@@ -633,6 +635,10 @@ struct BwdLayout {
   bool aj_global = false;  // small build without the LDS copy of the input site
   int64_t scratch_stride = 0, part_stride = 0;
   size_t hdr_bytes = 0, total = 0;
+  // caller memory of the two-call backward: each job's top-sweep states
+  int64_t states_elems[TN_MAX_SEGMENTS] = {};  // per syndrome
+  size_t states_ofs[TN_MAX_SEGMENTS] = {};     // bytes from the start of the buffer
+  size_t states_total = 0;
 };
 
 int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
@@ -688,8 +694,11 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
     // work and bottom regions, the stored top states (the shared rows once,
     // the rest per coset), environments and three temporaries
     const int S = std::min(H->shared_rows, H->nstep);
-    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems + (int64_t)(S + 4 * (H->nstep - S)) * H->mps_elems +
-                                               H->env_elems + 3 * H->tmp_elems);
+    const int64_t st_elems = (int64_t)(S + 4 * (H->nstep - S)) * H->mps_elems;
+    per_item = std::max<int64_t>(per_item, 2 * H->scratch_elems + st_elems + H->env_elems + 3 * H->tmp_elems);
+    bl->states_elems[ji] = st_elems;
+    bl->states_ofs[ji] = bl->states_total;
+    bl->states_total += align_up((size_t)segs[oi].count * (size_t)st_elems * real_bytes(L.precision));
     ++ji;
   }
   const int lb = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision)).bytes;
@@ -787,17 +796,28 @@ int tn_decode_batch_noalloc(const tn_segment* segs, int32_t nseg, double tie_tol
   return TN_OK;
 }
 
-int tn_coset_loglik_backward(const tn_segment* segs, int32_t nseg, const double* const* grad_logp,
-                             double* const* grad_log_rates, int32_t forward_done, void* workspace, size_t ws_bytes,
-                             void* stream) {
+}  // extern "C"
+
+namespace tnmld {
+namespace {
+
+// The backward launch in one of three modes (ADJ_FUSED, ADJ_TOP, ADJ_BOTTOM;
+// adjoint.hpp).  ADJ_TOP takes no gradient arrays and writes log Z / log P(s);
+// the other two accumulate into grad_log_rates.
+int run_backward(const tn_segment* segs, int32_t nseg, const double* const* grad_logp, double* const* grad_log_rates,
+                 int write_fwd, int mode, void* states, size_t states_bytes, void* workspace, size_t ws_bytes,
+                 void* stream) {
   BwdLayout bl;
   int rc = plan_backward(segs, nseg, &bl);
   if (rc) return rc;
-  if (!grad_logp || !grad_log_rates) return fail(TN_EINVAL, "null gradient arrays");
+  const bool grads = mode != ADJ_TOP;
+  if (grads && (!grad_logp || !grad_log_rates)) return fail(TN_EINVAL, "null gradient arrays");
   for (int i = 0; i < nseg; ++i) {
-    if (segs[i].count > 0 && (!grad_logp[i] || !grad_log_rates[i] || !segs[i].out_logp))
+    if (segs[i].count > 0 && (!segs[i].out_logp || (grads && (!grad_logp[i] || !grad_log_rates[i]))))
       return fail(TN_EINVAL, "backward needs grad_logp, grad_log_rates and out_logp for every segment");
   }
+  if (mode != ADJ_FUSED && (!states || states_bytes < bl.states_total))
+    return fail(TN_EINVAL, "states buffer too small: need " + std::to_string(bl.states_total));
   if (!workspace || ws_bytes < bl.total) return fail(TN_EINVAL, "workspace too small: need " + std::to_string(bl.total));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   unsigned* status = status_word(workspace);
@@ -806,34 +826,67 @@ int tn_coset_loglik_backward(const tn_segment* segs, int32_t nseg, const double*
   char* base = reinterpret_cast<char*>(workspace) + bl.hdr_bytes;
   double* partials = reinterpret_cast<double*>(base);
   char* scratch_base = base + align_up((size_t)bl.nwg * bl.part_stride * sizeof(double));
-  fill_zero_f64<<<256, 256, 0, st>>>(partials, (int64_t)bl.nwg * bl.part_stride);
+  if (grads) fill_zero_f64<<<256, 256, 0, st>>>(partials, (int64_t)bl.nwg * bl.part_stride);
   JobTable jt = bl.jt;
   for (int i = 0; i < jt.n; ++i) {
-    jt.j[i].gradp = grad_logp[bl.seg_of_job[i]];
+    jt.j[i].gradp = grads ? grad_logp[bl.seg_of_job[i]] : nullptr;
     jt.j[i].status = status;
+    jt.j[i].states = mode == ADJ_FUSED ? nullptr : static_cast<char*>(states) + bl.states_ofs[i];
+    jt.j[i].states_stride = bl.states_elems[i];
   }
   LdsLayout lay = lds_layout(bl.merged, real_bytes(bl.precision), fac_bytes(bl.precision), bl.aj_global);
-  int write_fwd = forward_done ? 0 : 1;
+  int flags = (write_fwd ? 1 : 0) | (mode << 1);
   int64_t sstride = bl.scratch_stride, pstride = bl.part_stride;
   if (bl.small) {
-    if (tnmld_small::launch_bwd_small(bl.precision, &jt, scratch_base, sstride, &lay, lay.bytes, write_fwd, partials,
+    if (tnmld_small::launch_bwd_small(bl.precision, &jt, scratch_base, sstride, &lay, lay.bytes, flags, partials,
                                       pstride, bl.nwg, st) != 0)
       return fail(TN_EDEVICE, "backward launch failed");
   } else {
     const void* kern = bwd_kernel_of(bl.precision);
     if ((rc = ensure_lds_attr(kern, lay.bytes))) return rc;
-    void* args[] = {&jt, &scratch_base, &sstride, &lay, &write_fwd, &partials, &pstride};
+    void* args[] = {&jt, &scratch_base, &sstride, &lay, &flags, &partials, &pstride};
     if (hipLaunchKernel(kern, dim3(bl.nwg), dim3(NT), args, lay.bytes, st) != hipSuccess)
       return fail(TN_EDEVICE, "backward launch failed");
   }
-  for (int i = 0; i < jt.n; ++i) {
-    const tn_segment& sg = segs[bl.seg_of_job[i]];
-    const int64_t len = (int64_t)sg.n_models * sg.d * sg.d * 3;
-    reduce_partials<<<(unsigned)((len + 255) / 256), 256, 0, st>>>(partials, pstride, bl.nwg, jt.j[i].part_ofs, len,
-                                                                   grad_log_rates[bl.seg_of_job[i]]);
-  }
+  if (grads)
+    for (int i = 0; i < jt.n; ++i) {
+      const tn_segment& sg = segs[bl.seg_of_job[i]];
+      const int64_t len = (int64_t)sg.n_models * sg.d * sg.d * 3;
+      reduce_partials<<<(unsigned)((len + 255) / 256), 256, 0, st>>>(partials, pstride, bl.nwg, jt.j[i].part_ofs,
+                                                                     len, grad_log_rates[bl.seg_of_job[i]]);
+    }
   if (hipGetLastError() != hipSuccess) return fail(TN_EDEVICE, "reduction launch failed");
   return TN_OK;
+}
+
+}  // namespace
+}  // namespace tnmld
+
+extern "C" {
+
+int tn_coset_loglik_backward(const tn_segment* segs, int32_t nseg, const double* const* grad_logp,
+                             double* const* grad_log_rates, int32_t forward_done, void* workspace, size_t ws_bytes,
+                             void* stream) {
+  return run_backward(segs, nseg, grad_logp, grad_log_rates, forward_done ? 0 : 1, ADJ_FUSED, nullptr, 0, workspace,
+                      ws_bytes, stream);
+}
+
+size_t tn_states_size(const tn_segment* segs, int32_t nseg) {
+  BwdLayout bl;
+  if (plan_backward(segs, nseg, &bl)) return 0;
+  return bl.states_total > 0 ? bl.states_total : 256;
+}
+
+int tn_coset_loglik_save(const tn_segment* segs, int32_t nseg, void* states, size_t states_bytes, void* workspace,
+                         size_t ws_bytes, void* stream) {
+  return run_backward(segs, nseg, nullptr, nullptr, 1, ADJ_TOP, states, states_bytes, workspace, ws_bytes, stream);
+}
+
+int tn_coset_loglik_backward_saved(const tn_segment* segs, int32_t nseg, const double* const* grad_logp,
+                                   double* const* grad_log_rates, const void* states, size_t states_bytes,
+                                   void* workspace, size_t ws_bytes, void* stream) {
+  return run_backward(segs, nseg, grad_logp, grad_log_rates, 0, ADJ_BOTTOM, const_cast<void*>(states), states_bytes,
+                      workspace, ws_bytes, stream);
 }
 
 int tn_code_stabilizers(int32_t d, int32_t* type_out, int32_t* support_out) {

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(NT) void fwd_kernel_small(JobTable jt, unsigned lon
 // Backward on 256-thread work-groups (see bwd_kernel in tnmld.hip).
 template <typename Real, typename Fac, int GM>
 __global__ __launch_bounds__(NT) void bwd_kernel_small(JobTable jt, char* scratch, int64_t scratch_stride,
-                                                        LdsLayout lay, int write_fwd, double* partials,
+                                                        LdsLayout lay, int flags, double* partials,
                                                         int64_t part_stride) {
   extern __shared__ __align__(16) uint8_t smem[];
   Real* scr = reinterpret_cast<Real*>(scratch + (int64_t)blockIdx.x * scratch_stride);
@@ -52,7 +52,8 @@ __global__ __launch_bounds__(NT) void bwd_kernel_small(JobTable jt, char* scratc
     int jb = 0;
     while (jb + 1 < jt.n && jt.j[jb + 1].item_begin <= item) ++jb;
     const JobDev& job = jt.j[jb];
-    adjoint_syndrome<Real, Fac, GM>(job, item - job.item_begin, smem, lay, scr, write_fwd, mypart + job.part_ofs);
+    adjoint_syndrome<Real, Fac, GM>(job, item - job.item_begin, smem, lay, scr, flags & 1, mypart + job.part_ofs,
+                                    flags >> 1);
     __syncthreads();
   }
 }
@@ -134,12 +135,12 @@ int small_bwd_wgs_per_cu(int precision, int lds_bytes) {
 
 // Enqueue the small backward kernel (jt, lay: the caller's JobTable / LdsLayout).
 int launch_bwd_small(int precision, const void* jt, char* scratch, int64_t stride, const void* lay, int lds_bytes,
-                     int write_fwd, double* partials, int64_t pstride, int nwg, hipStream_t st) {
+                     int flags, double* partials, int64_t pstride, int nwg, hipStream_t st) {
   const void* kern = bwd_kernel_of(precision);
   if (raise_lds(kern, lds_bytes) != 0) return -1;
   JobTable t = *reinterpret_cast<const JobTable*>(jt);
   LdsLayout l = *reinterpret_cast<const LdsLayout*>(lay);
-  void* args[] = {&t, &scratch, &stride, &l, &write_fwd, &partials, &pstride};
+  void* args[] = {&t, &scratch, &stride, &l, &flags, &partials, &pstride};
   if (hipLaunchKernel(kern, dim3(nwg), dim3(NT), args, (size_t)lds_bytes, st) != hipSuccess) return -1;
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -228,3 +228,13 @@ def test_adjoint_flop_counts(d, chi):
     assert 0 < i["environment_flops"] < i["flops"]
     tot = i["flops_syndrome"] + 4.0 * (i["bottom_sweep_flops"] + i["environment_flops"])
     assert abs(i["adjoint_flops_syndrome"] - tot) <= 1e-9 * tot
+
+
+def test_saved_state_entry_points_reject_bad_arguments(L):
+    """The two-call gradient's entry points check their arguments before any
+    device call: invalid segments give size 0 and TN_EINVAL."""
+    arr = (_lib.Segment * 1)(_seg(d=4))
+    assert L.tn_states_size(arr, 1) == 0
+    assert L.tn_coset_loglik_save(arr, 1, None, 0, None, 0, None) == _lib.TN_EINVAL
+    g = (ctypes.c_void_p * 1)(1)
+    assert L.tn_coset_loglik_backward_saved(arr, 1, g, g, None, 0, None, 0, None) == _lib.TN_EINVAL

@@ -516,6 +516,9 @@ def main():
     gemm_per_step = sum(len(s["syndromes"]) * tn.plan_info(s["d"], s["chi"], a.precision)["gemm_flops_syndrome"]
                         for s in segs_h)
     segs = inputs(a.precision)
+    # the forward kernel build each distinct (d, chi) of the batch runs on
+    shapes = {(s["d"], s["chi"]): tn.api.launch_shape(s["d"], s["chi"], a.precision) for s in segs_h}
+    kernels = sorted({"fwd_kernel_small" if sh[2] == 256 else "fwd_kernel" for sh in shapes.values()})
     print("bench: %s, %s, %d warmup + %d timed steps" % (workload, a.precision, a.warmup, a.steps),
           file=sys.stderr, flush=True)
     for _ in range(a.warmup):
@@ -559,7 +562,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_ALU_TFLOPS,
                      "traffic": measured_traffic(a.precision, a.count, a.workload),
-                     "flops_per_launch": flops_per_step, "kernel": "fwd_kernel"},
+                     "flops_per_launch": flops_per_step, "kernel": " + ".join(kernels)},
+        "launch": {"%d:%d" % k: {"group": v[0], "wg_per_cu": v[1], "threads": v[2]} for k, v in shapes.items()},
         "wall_s": wall,
     }
     if a.precision == "bf16":

@@ -5,8 +5,9 @@ marshals arguments.  See include/tnmld.h for the C ABI.
 """
 from ._lib import TNError, lib, LIB_PATH  # noqa: F401
 from .api import (SegmentInput, SegmentOutput, bitflip_plan_info, check_input_values, code_stabilizers,  # noqa: F401
-                  coset_loglik, coset_loglik_backward, coset_loglik_backward_saved, coset_loglik_save, decode, decode_bitflip, decode_bitflip_segments, decode_segments,
-                  decode_rounds, log_posterior, plan_info, set_tuning, states_bytes, workspace_bytes)
+                  coset_loglik, coset_loglik_backward, coset_loglik_backward_saved, coset_loglik_save, decode,
+                  decode_bitflip, decode_bitflip_segments, decode_rounds, decode_segments, log_posterior, plan_info,
+                  set_tuning, states_bytes, workspace_bytes)
 from .fit import fit_log_rates  # noqa: F401
 
 from . import tune as _tune  # noqa: E402
@@ -16,7 +17,7 @@ try:  # apply the autotuner's cached launch shapes (needs only the host library)
 except Exception:  # a missing or unreadable cache keeps the defaults
     pass
 
-__all__ = ["TNError", "SegmentInput", "SegmentOutput", "coset_loglik", "coset_loglik_backward", "log_posterior",
-           "decode", "decode_segments", "decode_bitflip", "decode_bitflip_segments", "bitflip_plan_info",
-           "check_input_values", "workspace_bytes", "fit_log_rates", "plan_info",
-           "set_tuning", "code_stabilizers", "lib", "LIB_PATH"]
+__all__ = ["TNError", "SegmentInput", "SegmentOutput", "coset_loglik", "coset_loglik_backward", "coset_loglik_save",
+           "coset_loglik_backward_saved", "states_bytes", "log_posterior", "decode", "decode_segments",
+           "decode_rounds", "decode_bitflip", "decode_bitflip_segments", "bitflip_plan_info", "check_input_values",
+           "workspace_bytes", "fit_log_rates", "plan_info", "set_tuning", "code_stabilizers", "lib", "LIB_PATH"]

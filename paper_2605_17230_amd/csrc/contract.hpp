@@ -199,8 +199,11 @@ struct Work {
   const double* meas;
 };
 
-template <typename Real, typename Fac>
-__device__ inline Work<Real, Fac> carve(uint8_t* smem, const LdsLayout& lay, int* flags) {
+// XG: the LQ matrix X is in the work-group's global scratch, lay.xg bytes from
+// gbase (a layout with lay.X < 0); else in LDS.  A compile-time choice, so that
+// the accesses of either kind keep their address space.
+template <typename Real, typename Fac, bool XG = false>
+__device__ inline Work<Real, Fac> carve(uint8_t* smem, const LdsLayout& lay, int* flags, uint8_t* gbase = nullptr) {
   Work<Real, Fac> w;
   w.fbits = smem + lay.fbits;
   w.syn = smem + lay.syn;
@@ -212,7 +215,8 @@ __device__ inline Work<Real, Fac> carve(uint8_t* smem, const LdsLayout& lay, int
   w.T = reinterpret_cast<Real*>(smem + lay.T);
   w.L = reinterpret_cast<Real*>(smem + lay.L);
   w.C = reinterpret_cast<Real*>(smem + lay.C);
-  w.X = reinterpret_cast<Fac*>(smem + lay.X);
+  if constexpr (XG) w.X = reinterpret_cast<Fac*>(gbase + lay.xg);
+  else w.X = reinterpret_cast<Fac*>(smem + lay.X);
   w.tau = reinterpret_cast<Fac*>(smem + lay.tau);
   w.diag = reinterpret_cast<Fac*>(smem + lay.diag);
   w.vtmp = reinterpret_cast<Fac*>(smem + lay.v);
@@ -286,8 +290,9 @@ __device__ inline void mps_ones(Real* scr, const int64_t* region, const uint8_t*
 // right-canonical form (right-to-left LQ), then move the centre back
 // left-to-right by QR, truncating the bonds the plan cuts by SVD.  The MPS is
 // left normalised; log-norms go to `logscale`.  Returns false when the state
-// vanished (the coset has probability zero).  Collective.
-template <typename Real, typename Fac, int GM>
+// vanished (the coset has probability zero).  XG: the LQ matrix is in global
+// scratch (carve<..., true>).  Collective.
+template <typename Real, typename Fac, int GM, bool XG = false>
 __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, const double* rates, Real* scr,
                          const int64_t* region, Work<Real, Fac>& w, double& logscale) {
   const int tid = threadIdx.x;
@@ -404,8 +409,25 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
         for_2d(mJ, k, [&](int r, int c) { L[r * k + c] = Real(lval(r, c)); });
       }
       __syncthreads();
-      lq_form_q_any<Fac>(X, mJ, nn, nn, tau, vtmp);
-      for (int e = tid; e < k * nn; e += NT) g[e] = Real(X[e]);
+      bool staged = false;
+      if constexpr (XG && sizeof(Fac) == 4) {
+        // X in global scratch (FP32 factorisations: the plans that need it):
+        // the reflectors are staged through LDS and the rows of Q written
+        // straight to the site region
+        if (lq_regs_fit<Fac>(mJ, nn)) {
+          if (nn <= 128)
+            lq_form_q_staged<Fac, Real, 8>((const glb_t<Fac>*)X, mJ, nn, nn, (const lds_t<Fac>*)tau,
+                                           (lds_t<Fac>*)vtmp, (glb_t<Real>*)g, nn);
+          else
+            lq_form_q_staged<Fac, Real, 16>((const glb_t<Fac>*)X, mJ, nn, nn, (const lds_t<Fac>*)tau,
+                                            (lds_t<Fac>*)vtmp, (glb_t<Real>*)g, nn);
+          staged = true;
+        }
+      }
+      if (!staged) {
+        lq_form_q_any<Fac>(X, mJ, nn, nn, tau, vtmp);
+        for (int e = tid; e < k * nn; e += NT) g[e] = Real(X[e]);
+      }
       __syncthreads();
     }
     // L is 1x1: the norm of the MPO-applied state
@@ -575,8 +597,9 @@ __device__ inline void mps_pack(const Real* scr, const int64_t* region, int nsit
 // H->shared_rows touch no qubit of the logical representatives, so they are
 // contracted once; the MPS after them is saved to snap (mps_elems) and each
 // coset continues from it.  Writes logz[b][label] for the four cosets; a
-// prefix that vanishes makes all four -inf.  Collective.
-template <typename Real, typename Fac, int GM = GEMM_VALU>
+// prefix that vanishes makes all four -inf.  XG: the layout keeps the LQ matrix
+// in global scratch (lay.X < 0, lay.xg bytes from scr).  Collective.
+template <typename Real, typename Fac, int GM = GEMM_VALU, bool XG = false>
 __device__ void contract_syndrome(const JobDev& job, int64_t b, uint8_t* smem, const LdsLayout& lay, Real* scr,
                                   Real* snap) {
   const uint8_t* plan = job.plan;
@@ -590,7 +613,7 @@ __device__ void contract_syndrome(const JobDev& job, int64_t b, uint8_t* smem, c
   const int16_t* fin = reinterpret_cast<const int16_t*>(plan + H->final_ofs);
   __shared__ int s_flags[2];
   __shared__ int s_label;
-  Work<Real, Fac> w = carve<Real, Fac>(smem, lay, s_flags);
+  Work<Real, Fac> w = carve<Real, Fac, XG>(smem, lay, s_flags, reinterpret_cast<uint8_t*>(scr));
   const ItemCheck ck = check_item(job, b, n, m);
   if (!ck.valid) {  // defined outputs (Z = 0 for every coset) and the status bit
     if (threadIdx.x < 4) job.logz[b * 4 + threadIdx.x] = -INFINITY;
@@ -620,7 +643,7 @@ __device__ void contract_syndrome(const JobDev& job, int64_t b, uint8_t* smem, c
   double base = 0.0;
   bool alive = true;
   for (int u = 0; u < ushare && alive; ++u)
-    alive = row_step<Real, Fac, GM>(steps + (int64_t)u * nsite, nsite, codes, rates, scr, region, w, base);
+    alive = row_step<Real, Fac, GM, XG>(steps + (int64_t)u * nsite, nsite, codes, rates, scr, region, w, base);
   if (!alive) {
     for (int mlog = 0; mlog < 4; ++mlog) {
       const int label = prep_reference(H, checks, syn_last, mlog, w.syn, w.fbits, &s_label);
@@ -638,7 +661,7 @@ __device__ void contract_syndrome(const JobDev& job, int64_t b, uint8_t* smem, c
     double logscale = base;
     bool ok = true;
     for (int u = ushare; u < nstep && ok; ++u)
-      ok = row_step<Real, Fac, GM>(steps + (int64_t)u * nsite, nsite, codes, rates, scr, region, w, logscale);
+      ok = row_step<Real, Fac, GM, XG>(steps + (int64_t)u * nsite, nsite, codes, rates, scr, region, w, logscale);
     const double lz = finish_logz(ok ? logscale + mps_close<Real, Fac>(scr, region, fin, nsite, w.sig) : -INFINITY);
     if (threadIdx.x == 0) {
       job.logz[b * 4 + label] = lz;

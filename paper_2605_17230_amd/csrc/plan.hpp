@@ -146,6 +146,9 @@ struct LdsLayout {
   // three contraction temporaries, the top and bottom site, two bonds of
   // environment
   int32_t gP, gA, gF, gE, gR;
+  // X < 0: the LQ matrix of the right-to-left sweep lives in the work-group's
+  // global scratch, xg bytes from its base (set by the launch)
+  int32_t xg;
   int32_t bytes;
 };
 
@@ -159,14 +162,18 @@ constexpr size_t kStatusOffset = 128;
 
 // aj_global: the MPO step reads the input site tensor from its scratch region
 // instead of an LDS copy (o.Aj = -1), to fit two work-groups of the 256-thread
-// build in a CU.
-inline LdsLayout lds_layout(const PlanHeader& h, int rb, int fb, bool aj_global = false) {
+// build in a CU.  x_global: the LQ matrix of the right-to-left sweep (the
+// largest buffer, m x qo kr) lives in global scratch too (o.X = -1; the launch
+// sets o.xg); its explicit Q then stages one reflector at a time through LDS.
+inline LdsLayout lds_layout(const PlanHeader& h, int rb, int fb, bool aj_global = false, bool x_global = false) {
   LdsLayout o{};
   int32_t p = 0;
   o.Aj = aj_global ? -1 : p;
   if (!aj_global) p += pad64b((int64_t)h.max_Aj * rb);
   o.T = p; p += pad64b((int64_t)h.max_T * rb);
-  o.X = p; p += pad64b((int64_t)h.max_X * fb);
+  o.X = x_global ? -1 : p;
+  if (!x_global) p += pad64b((int64_t)h.max_X * fb);
+  o.xg = 0;
   o.L = p; p += pad64b((int64_t)h.max_L * rb);
   const int32_t rl_end = p;
   p = 0;

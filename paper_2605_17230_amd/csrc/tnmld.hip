@@ -39,7 +39,7 @@
 
 // The forward kernel built for 256-thread work-groups (tnmld_small.hip).
 namespace tnmld_small {
-int small_wgs_per_cu(int precision, int lds_bytes);
+int small_wgs_per_cu(int precision, int lds_bytes, bool xg);
 int launch_fwd_small(int precision, const void* jt, unsigned long long* counter, char* scratch, int64_t stride,
                      int64_t snap_ofs, const void* lay, int lds_bytes, int nwg, hipStream_t st);
 int small_bwd_wgs_per_cu(int precision, int lds_bytes);
@@ -369,8 +369,15 @@ bool small_plan(const PlanHeader& h, int precision) {
   const int limit = kLdsPerCU / 2 - 256;
   int lb = lds_layout(h, real_bytes(precision), fac_bytes(precision)).bytes;
   if (lb > limit) lb = lds_layout(h, real_bytes(precision), fac_bytes(precision), true).bytes;
+  // and if that is not enough (FP32 factorisations), the LQ matrix of the
+  // right-to-left sweep goes to the work-group's scratch as well
+  bool xg = false;
+  if (lb > limit && fac_bytes(precision) == 4) {
+    lb = lds_layout(h, real_bytes(precision), fac_bytes(precision), true, true).bytes;
+    xg = true;
+  }
   if (lb > limit) return false;
-  return tnmld_small::small_wgs_per_cu(precision, lb) >= 2;
+  return tnmld_small::small_wgs_per_cu(precision, lb, xg) >= 2;
 }
 
 constexpr int kMaxLaunches = 2 * (TN_FP32_PLAIN + 1);  // one per precision and size class
@@ -379,6 +386,7 @@ struct Launch {
   const Plan* host_plan[TN_MAX_SEGMENTS];  // plan of each job (host copy)
   bool small;      // 256-thread build
   bool aj_global;  // small launch whose MPO step reads the input site from its region (LDS)
+  bool x_global;   // small launch whose LQ matrix lives in the work-group's scratch (LDS)
   int precision;
   JobTable jt;  // forward items are syndromes
   PlanHeader merged;
@@ -389,6 +397,20 @@ struct Launch {
 
 constexpr size_t kAlign = kWorkspaceAlign;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Bytes of one work-group's scratch: the site regions and the saved MPS of the
+// rows common to the cosets, then (x_global) the LQ matrix.
+size_t group_bytes(const Launch& L) {
+  size_t b = align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
+  if (L.x_global) b += align_up((size_t)L.merged.max_X * fac_bytes(L.precision));
+  return b;
+}
+
+LdsLayout launch_layout(const Launch& L) {
+  LdsLayout lay = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision), L.aj_global, L.x_global);
+  if (L.x_global) lay.xg = (int32_t)align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
+  return lay;
+}
 
 // Workspace header (the first kAlign bytes): one work counter per launch, then
 // the status word of the last call (ST_* bits, read by tn_workspace_status)
@@ -457,15 +479,16 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
     }
     L.jt.nitems = items;
     L.aj_global = small && lds_layout(L.merged, real_bytes(prec), fac_bytes(prec)).bytes > kLdsPerCU / 2 - 256;
+    L.x_global = small && lds_layout(L.merged, real_bytes(prec), fac_bytes(prec), true).bytes > kLdsPerCU / 2 - 256;
     if (L.jt.n > 0) out->push_back(L);
   }
   size_t bytes = align_up(sizeof(unsigned long long) * kMaxLaunches);
   for (auto& L : *out) {
     if (L.merged.max_bond > NT) return fail(TN_EUNSUPPORTED, "bond dimension above the work-group size");
-    const int lb = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision), L.aj_global).bytes;
+    const int lb = launch_layout(L).bytes;
     int w = wgs_for(lb, fwd_kernel_of(L.precision));
     if (L.small) {
-      const int ws = tnmld_small::small_wgs_per_cu(L.precision, lb);
+      const int ws = tnmld_small::small_wgs_per_cu(L.precision, lb, L.x_global);
       w = std::min(kLdsPerCU / (lb + 256), ws > 0 ? ws : 1);
       if (L.nwg > 0) w = std::min(w, L.nwg);  // tuned for the 256-thread build
     } else if (L.nwg > 0) {
@@ -474,7 +497,7 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
     if (w < 1) return fail(TN_EUNSUPPORTED, "LDS of the merged plans exceeds one CU");
     L.nwg = w * di.cus;
     *nwg = std::max(*nwg, L.nwg);
-    bytes += (size_t)L.nwg * align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
+    bytes += (size_t)L.nwg * group_bytes(L);
   }
   *ws_bytes = bytes;
   return TN_OK;
@@ -482,11 +505,11 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
 
 template <typename Real, typename Fac, int GM>
 int launch_fwd(const Launch& L, int nwg, char* ws_scratch, unsigned long long* counter, hipStream_t st) {
-  LdsLayout lay = lds_layout(L.merged, sizeof(Real), sizeof(Fac));
+  LdsLayout lay = launch_layout(L);
   auto kern = fwd_kernel<Real, Fac, GM>;
   if (int rc = ensure_lds_attr(reinterpret_cast<const void*>(kern), lay.bytes)) return rc;
   zero_counter<<<1, 64, 0, st>>>(counter);
-  const int64_t stride = (int64_t)align_up((size_t)(L.scratch_elems + L.mps_elems) * sizeof(Real));
+  const int64_t stride = (int64_t)group_bytes(L);
   const int64_t snap_ofs = L.scratch_elems;
   hipLaunchKernelGGL(kern, dim3(nwg), dim3(NT), lay.bytes, st, L.jt, counter, ws_scratch, stride, snap_ofs, lay);
   if (hipGetLastError() != hipSuccess) return fail(TN_EDEVICE, "kernel launch failed");
@@ -505,10 +528,10 @@ int enqueue_forward(std::vector<Launch>& launches, char* header, char* regions, 
     for (int i = 0; i < L.jt.n; ++i) L.jt.j[i].status = status;
     unsigned long long* counter = reinterpret_cast<unsigned long long*>(header) + li;
     char* scr = regions + off;
-    off += (size_t)L.nwg * align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
+    off += (size_t)L.nwg * group_bytes(L);
     if (L.small) {
-      const LdsLayout lay = lds_layout(L.merged, real_bytes(L.precision), fac_bytes(L.precision), L.aj_global);
-      const int64_t stride = (int64_t)align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
+      const LdsLayout lay = launch_layout(L);
+      const int64_t stride = (int64_t)group_bytes(L);
       if (tnmld_small::launch_fwd_small(L.precision, &L.jt, counter, scr, stride, L.scratch_elems, &lay, lay.bytes,
                                         L.nwg, st) != 0)
         return fail(TN_EDEVICE, "kernel launch failed");
@@ -601,7 +624,7 @@ int run_forward_noalloc(const tn_segment* segs, int32_t nseg, void* stream) {
   const size_t avail = kNoAllocBytes - kAlign - kNoAllocPlanBytes;
   size_t per_round = 0, full = 0;
   for (auto& L : launches) {
-    const size_t pw = align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
+    const size_t pw = group_bytes(L);
     per_round += pw;
     full += (size_t)L.nwg * pw;
   }
@@ -611,10 +634,8 @@ int run_forward_noalloc(const tn_segment* segs, int32_t nseg, void* stream) {
   if (full > avail) {
     const double f = (double)avail / (double)full;
     for (auto& L : launches) {
-      const size_t pw = align_up((size_t)(L.scratch_elems + L.mps_elems) * real_bytes(L.precision));
       int w = (int)((double)L.nwg * f);
       L.nwg = std::max(1, std::min(L.nwg, w));
-      (void)pw;
     }
   }
   for (const auto& kv : placed)

@@ -8,6 +8,7 @@
 
 #include <map>
 #include <mutex>
+#include <tuple>
 
 #define TNMLD_NT 256
 #define tnmld tnmld_small
@@ -19,7 +20,7 @@
 
 namespace tnmld_small {
 
-template <typename Real, typename Fac, int GM>
+template <typename Real, typename Fac, int GM, bool XG = false>
 __global__ __launch_bounds__(NT) void fwd_kernel_small(JobTable jt, unsigned long long* counter, char* scratch,
                                                         int64_t scratch_stride, int64_t snap_ofs, LdsLayout lay) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -35,7 +36,7 @@ __global__ __launch_bounds__(NT) void fwd_kernel_small(JobTable jt, unsigned lon
     int jb = 0;
     while (jb + 1 < jt.n && jt.j[jb + 1].item_begin <= item) ++jb;
     const JobDev& job = jt.j[jb];
-    contract_syndrome<Real, Fac, GM>(job, item - job.item_begin, smem, lay, scr, snap);
+    contract_syndrome<Real, Fac, GM, XG>(job, item - job.item_begin, smem, lay, scr, snap);
     __syncthreads();
   }
 }
@@ -63,7 +64,15 @@ __global__ void zero_one(unsigned long long* c) {
 }
 
 namespace {
-const void* kernel_of(int precision) {
+// xg: the variant whose LQ matrix lives in global scratch (built for the forms
+// with FP32 factorisations, the only ones whose plans need it)
+const void* kernel_of(int precision, bool xg = false) {
+  if (xg) {
+    if (precision == TN_BF16)
+      return reinterpret_cast<const void*>(fwd_kernel_small<float, float, BF16_GEMM_MODE, true>);
+    if (precision == TN_FP32_PLAIN) return reinterpret_cast<const void*>(fwd_kernel_small<float, float, GEMM_VALU, true>);
+    return nullptr;
+  }
   if (precision == TN_FP64) return reinterpret_cast<const void*>(fwd_kernel_small<double, double, GEMM_VALU>);
   if (precision == TN_FP32) return reinterpret_cast<const void*>(fwd_kernel_small<float, double, GEMM_VALU>);
   if (precision == TN_BF16) return reinterpret_cast<const void*>(fwd_kernel_small<float, float, BF16_GEMM_MODE>);
@@ -91,21 +100,21 @@ int raise_lds(const void* kern, int bytes) {
 
 // Work-groups of the small kernel that one CU holds with lds_bytes of LDS
 // (0 if the runtime cannot say).
-int small_wgs_per_cu(int precision, int lds_bytes) {
-  static std::map<std::pair<int, int>, int> cache;
+int small_wgs_per_cu(int precision, int lds_bytes, bool xg) {
+  static std::map<std::tuple<int, int, bool>, int> cache;
   static std::mutex mu;
   {
     std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find(std::make_pair(precision, lds_bytes));
+    auto it = cache.find(std::make_tuple(precision, lds_bytes, xg));
     if (it != cache.end()) return it->second;
   }
-  const void* kern = kernel_of(precision);
+  const void* kern = kernel_of(precision, xg);
   int nb = 0;
-  if (raise_lds(kern, lds_bytes) != 0 ||
+  if (!kern || raise_lds(kern, lds_bytes) != 0 ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, (size_t)lds_bytes) != hipSuccess)
     nb = 0;
   std::lock_guard<std::mutex> lk(mu);
-  cache[std::make_pair(precision, lds_bytes)] = nb;
+  cache[std::make_tuple(precision, lds_bytes, xg)] = nb;
   return nb;
 }
 
@@ -113,11 +122,11 @@ int small_wgs_per_cu(int precision, int lds_bytes) {
 // the caller's JobTable and LdsLayout (same definitions, other namespace).
 int launch_fwd_small(int precision, const void* jt, unsigned long long* counter, char* scratch, int64_t stride,
                      int64_t snap_ofs, const void* lay, int lds_bytes, int nwg, hipStream_t st) {
-  const void* kern = kernel_of(precision);
-  if (raise_lds(kern, lds_bytes) != 0) return -1;
+  LdsLayout l = *reinterpret_cast<const LdsLayout*>(lay);
+  const void* kern = kernel_of(precision, l.X < 0);
+  if (!kern || raise_lds(kern, lds_bytes) != 0) return -1;
   zero_one<<<1, 64, 0, st>>>(counter);
   JobTable t = *reinterpret_cast<const JobTable*>(jt);
-  LdsLayout l = *reinterpret_cast<const LdsLayout*>(lay);
   void* args[] = {&t, &counter, &scratch, &stride, &snap_ofs, &l};
   if (hipLaunchKernel(kern, dim3(nwg), dim3(NT), args, (size_t)lds_bytes, st) != hipSuccess) return -1;
   return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -41,18 +41,26 @@ void run_block(F f) {
 template <typename Real, typename Fac>
 int forward(int d, int chi, int group, const double* rates, int n_models, const int32_t* model_index,
             const uint8_t* syn, int count, double* logz, unsigned* status, int rounds = 1,
-            const double* meas = nullptr) {
+            const double* meas = nullptr, bool xg = false) {
   Plan p;
   if (!build_plan(d, chi, group, &p, rounds).empty()) return -1;
-  const LdsLayout lay = lds_layout(p.h, sizeof(Real), sizeof(Fac));
-  std::vector<double> smem(lay.bytes / 8 + 16), scr(p.h.scratch_elems * sizeof(Real) / 8 + 16),
+  // xg: the layout of the 256-thread launches that keep the input site and the
+  // LQ matrix in the work-group's scratch (the LQ matrix after the site regions)
+  LdsLayout lay = lds_layout(p.h, sizeof(Real), sizeof(Fac), xg, xg);
+  const int64_t sbytes = (p.h.scratch_elems * (int64_t)sizeof(Real) + 255) / 256 * 256;
+  if (xg) lay.xg = (int32_t)sbytes;
+  std::vector<double> smem(lay.bytes / 8 + 16), scr((sbytes + (int64_t)p.h.max_X * sizeof(Fac)) / 8 + 16),
       snap(p.h.mps_elems * sizeof(Real) / 8 + 16);
   JobDev job{p.blob.data(), rates, model_index, syn, logz, nullptr, nullptr, count, 0, 0, n_models, rounds, status,
              meas};
   Barriers bars;
   for (int b = 0; b < count; ++b)
     run_block([&](int) {
-      contract_syndrome<Real, Fac>(job, b, (uint8_t*)smem.data(), lay, (Real*)scr.data(), (Real*)snap.data());
+      if (xg)
+        contract_syndrome<Real, Fac, GEMM_VALU, true>(job, b, (uint8_t*)smem.data(), lay, (Real*)scr.data(),
+                                                      (Real*)snap.data());
+      else
+        contract_syndrome<Real, Fac>(job, b, (uint8_t*)smem.data(), lay, (Real*)scr.data(), (Real*)snap.data());
     });
   return 0;
 }
@@ -85,6 +93,17 @@ extern "C" int emu_forward(int d, int chi, int precision, int group, const doubl
   if (precision == 0) return forward<double, double>(d, chi, group, rates, 1, nullptr, syn, count, logz, nullptr);
   if (precision == 1) return forward<float, double>(d, chi, group, rates, 1, nullptr, syn, count, logz, nullptr);
   return forward<float, float>(d, chi, group, rates, 1, nullptr, syn, count, logz, nullptr);
+}
+
+// the same with the input site and the LQ matrix in global scratch (the
+// staged explicit Q of the right-to-left sweep)
+extern "C" int emu_forward_xg(int d, int chi, int precision, int group, const double* rates, const uint8_t* syn,
+                              int count, double* logz) {
+  if (precision == 0)
+    return forward<double, double>(d, chi, group, rates, 1, nullptr, syn, count, logz, nullptr, 1, nullptr, true);
+  if (precision == 1)
+    return forward<float, double>(d, chi, group, rates, 1, nullptr, syn, count, logz, nullptr, 1, nullptr, true);
+  return forward<float, float>(d, chi, group, rates, 1, nullptr, syn, count, logz, nullptr, 1, nullptr, true);
 }
 
 // the same with noise models selected per syndrome and the call's status word

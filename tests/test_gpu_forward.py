@@ -269,6 +269,28 @@ def test_c3_full_batch_vs_exact(dev, prec):
     oracle alone): per-coset |delta log Z| by posterior band and |delta log P|
     under the form's bars, classes equal on >= 99.9 % and wherever the
     oracle's top-two gap exceeds the error bound."""
+    check_c3(dev, prec)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["bf16", "fp32plain"])
+@pytest.mark.parametrize("shape", [(2, 1, 512), (2, 2, 256)])
+def test_c3_launch_shapes_vs_exact(dev, prec, shape):
+    """C3 under each launch shape of its two columns per site, whatever the
+    tuned default: one 512-thread work-group per CU, and two 256-thread ones,
+    which keep the input site and the LQ matrix of the right-to-left sweep in
+    their scratch (the rest fills half of a CU's LDS) and stage the reflectors
+    of the explicit Q through LDS.  Same bars, same oracle values."""
+    tn.set_tuning(17, 32, prec, *shape)
+    try:
+        assert tuple(tn.api.launch_shape(17, 32, prec)) == shape
+        check_c3(dev, prec)
+    finally:
+        tn.set_tuning(17, 32, prec)  # back to the default, then the tuned shapes
+        tn.tune.load()
+
+
+def check_c3(dev, prec):
     import warnings
     ref = np.loadtxt(GOLDEN_C3)
     r = synth.depolarizing(17, 0.12)

@@ -36,6 +36,22 @@ def emu():
     return L
 
 
+@pytest.fixture(scope="module")
+def emu256():
+    """The same sources built for 256-thread work-groups (the second build of
+    the forward kernel: four rows per lane group in the register LQ)."""
+    lib = os.path.join(EMU, "_build", "libemu256.so")
+    os.makedirs(os.path.dirname(lib), exist_ok=True)
+    subprocess.check_call(["g++", "-O2", "-std=c++20", "-shared", "-fPIC", "-DTNMLD_NT=256", "-I", CSRC, "-I", EMU,
+                           os.path.join(EMU, "emu_main.cpp"), os.path.join(CSRC, "plan.cpp"), "-o", lib,
+                           "-lpthread"])
+    L = ctypes.CDLL(lib)
+    P = ctypes.c_void_p
+    L.emu_forward.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_int, P]
+    L.emu_forward_xg.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_int, P]
+    return L
+
+
 def forward(L, d, chi, prec, group, rates, syn):
     rates = np.ascontiguousarray(rates, np.float64)
     syn = np.ascontiguousarray(syn, np.uint8)
@@ -165,3 +181,24 @@ def test_d3_two_rounds_exact(emu):
     ref = oracle.phen_transfer(d, 2, r, q, syn)
     assert st[0] == 0
     assert np.max(np.abs(out - ref) / np.maximum(1.0, np.abs(ref))) < 1e-12
+
+
+@pytest.mark.parametrize("chi,prec,group", [(0, 3, 2), (2, 0, 1)])
+def test_lq_matrix_in_global_scratch(emu256, chi, prec, group):
+    """The layout of the 256-thread launches whose LQ matrix does not fit LDS
+    (input site and LQ matrix in the work-group's scratch; with FP32
+    factorisations the explicit Q stages one reflector at a time through LDS)
+    gives the same log Z, bit for bit, as the LDS layout: the same operations in
+    the same order per row.  d = 3, exact (two columns per site) and truncated."""
+    d = 3
+    rates = synth.inhomogeneous(d, 0.01, 0.15, seed=11)
+    syn = np.ascontiguousarray(synth.sample(d, rates, 1, seed=12)["syndromes"])
+    r = np.ascontiguousarray(rates)
+    a = np.full((1, 4), np.nan)
+    b = np.full((1, 4), np.nan)
+    assert emu256.emu_forward(d, chi, prec, group, r.ctypes.data, syn.ctypes.data, 1, a.ctypes.data) == 0
+    assert emu256.emu_forward_xg(d, chi, prec, group, r.ctypes.data, syn.ctypes.data, 1, b.ctypes.data) == 0
+    assert np.array_equal(a, b)
+    ref = oracle.transfer(d, rates, syn)
+    fin = np.isfinite(ref)
+    assert np.max(np.abs(b[fin] - ref[fin])) < (1e-4 if prec == 3 else 1e-3)

@@ -659,22 +659,25 @@ __device__ __attribute__((noinline)) void lq_form_q_staged(const glb_t<Fac>* X, 
     }
     const lds_t<Fac>* v = vb + (i & 1) * W + lane;
     const Fac t = tau[i];
-    // the staged row is read per row slot, as lq_form_q_regs reads X: no
-    // register copy of it next to the four slots
+    // one register copy of the staged row serves all row slots (reading it per
+    // slot and per use would make the step LDS-bound)
+    Fac vv[NPL];
+#pragma unroll
+    for (int c = 0; c < NPL; ++c) vv[c] = v[16 * c];
 #pragma unroll
     for (int j = 0; j < RPG; ++j) {
       const int r = lq_q_row(j, grp, NG);
       if (r == i) {
 #pragma unroll
-        for (int c = 0; c < NPL; ++c) q[j][c] = (lane + 16 * c == r ? Fac(1) : Fac(0)) - t * v[16 * c];
+        for (int c = 0; c < NPL; ++c) q[j][c] = (lane + 16 * c == r ? Fac(1) : Fac(0)) - t * vv[c];
       } else if (r > i && r < k) {
         Fac dp[4] = {Fac(0), Fac(0), Fac(0), Fac(0)};
 #pragma unroll
-        for (int c = 0; c < NPL; ++c) dp[c & 3] += q[j][c] * v[16 * c];
+        for (int c = 0; c < NPL; ++c) dp[c & 3] += q[j][c] * vv[c];
         const Fac dot = group_sum((dp[0] + dp[1]) + (dp[2] + dp[3]), 16);
         const Fac w = Fac(dot) * t;
 #pragma unroll
-        for (int c = 0; c < NPL; ++c) q[j][c] -= w * v[16 * c];
+        for (int c = 0; c < NPL; ++c) q[j][c] -= w * vv[c];
       }
     }
     if (i > 0) {

@@ -359,24 +359,36 @@ int validate(const tn_segment* segs, int32_t nseg) {
 // kernel when at least two of its work-groups fit a CU (LDS and registers):
 // in practice chi <= 24, the larger plans need more than half the LDS.
 constexpr int kSmallNT = 256;
+
+// LDS of the 256-thread build within half a CU: the plain layout, else without
+// the MPO step's LDS copy of the input site (read from its site region), else
+// (FP32 factorisations) with the LQ matrix of the right-to-left sweep in the
+// work-group's scratch, which frees enough of that phase for the input site's
+// copy to return, else with both in scratch.  Returns the bytes, or -1.
+int small_layout(const PlanHeader& h, int precision, bool* aj_global, bool* x_global) {
+  const int limit = kLdsPerCU / 2 - 256;
+  const int rb = real_bytes(precision), fb = fac_bytes(precision);
+  for (int v = 0; v < 4; ++v) {
+    const bool aj = v == 1 || v == 3, xg = v >= 2;
+    if (xg && fb != 4) break;
+    const int lb = lds_layout(h, rb, fb, aj, xg).bytes;
+    if (lb <= limit) {
+      *aj_global = aj;
+      *x_global = xg;
+      return lb;
+    }
+  }
+  return -1;
+}
+
 bool small_plan(const PlanHeader& h, int precision) {
   // rows the 256-thread build keeps in registers: 4 per 16-lane group with
   // FP32 factorisations, 2 with FP64 ones
   const int rpg = fac_bytes(precision) == 4 ? 4 : 2;
   if (h.max_m > rpg * (kSmallNT / 16) || h.max_n > 256 || h.max_bond > kSmallNT) return false;
-  // half the LDS of a CU; if the input site's LDS copy is what does not fit,
-  // the MPO step reads it from the site region instead
-  const int limit = kLdsPerCU / 2 - 256;
-  int lb = lds_layout(h, real_bytes(precision), fac_bytes(precision)).bytes;
-  if (lb > limit) lb = lds_layout(h, real_bytes(precision), fac_bytes(precision), true).bytes;
-  // and if that is not enough (FP32 factorisations), the LQ matrix of the
-  // right-to-left sweep goes to the work-group's scratch as well
-  bool xg = false;
-  if (lb > limit && fac_bytes(precision) == 4) {
-    lb = lds_layout(h, real_bytes(precision), fac_bytes(precision), true, true).bytes;
-    xg = true;
-  }
-  if (lb > limit) return false;
+  bool aj = false, xg = false;
+  const int lb = small_layout(h, precision, &aj, &xg);
+  if (lb < 0) return false;
   return tnmld_small::small_wgs_per_cu(precision, lb, xg) >= 2;
 }
 
@@ -478,8 +490,13 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
       if (tw > 0) L.nwg = L.nwg ? std::min(L.nwg, tw) : tw;  // per-CU count for now
     }
     L.jt.nitems = items;
-    L.aj_global = small && lds_layout(L.merged, real_bytes(prec), fac_bytes(prec)).bytes > kLdsPerCU / 2 - 256;
-    L.x_global = small && lds_layout(L.merged, real_bytes(prec), fac_bytes(prec), true).bytes > kLdsPerCU / 2 - 256;
+    L.aj_global = L.x_global = false;
+    if (small && small_layout(L.merged, prec, &L.aj_global, &L.x_global) < 0) {
+      // plans that fit one by one, merged: the most compact layout (the
+      // work-groups per CU below follow from its LDS)
+      L.aj_global = true;
+      L.x_global = fac_bytes(prec) == 4;
+    }
     if (L.jt.n > 0) out->push_back(L);
   }
   size_t bytes = align_up(sizeof(unsigned long long) * kMaxLaunches);

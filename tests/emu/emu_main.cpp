@@ -44,9 +44,9 @@ int forward(int d, int chi, int group, const double* rates, int n_models, const 
             const double* meas = nullptr, bool xg = false) {
   Plan p;
   if (!build_plan(d, chi, group, &p, rounds).empty()) return -1;
-  // xg: the layout of the 256-thread launches that keep the input site and the
-  // LQ matrix in the work-group's scratch (the LQ matrix after the site regions)
-  LdsLayout lay = lds_layout(p.h, sizeof(Real), sizeof(Fac), xg, xg);
+  // xg: the layout of the 256-thread launches that keep the LQ matrix of the
+  // right-to-left sweep in the work-group's scratch (after the site regions)
+  LdsLayout lay = lds_layout(p.h, sizeof(Real), sizeof(Fac), false, xg);
   const int64_t sbytes = (p.h.scratch_elems * (int64_t)sizeof(Real) + 255) / 256 * 256;
   if (xg) lay.xg = (int32_t)sbytes;
   std::vector<double> smem(lay.bytes / 8 + 16), scr((sbytes + (int64_t)p.h.max_X * sizeof(Fac)) / 8 + 16),

@@ -186,8 +186,8 @@ def test_d3_two_rounds_exact(emu):
 @pytest.mark.parametrize("chi,prec,group", [(0, 3, 2), (2, 0, 1)])
 def test_lq_matrix_in_global_scratch(emu256, chi, prec, group):
     """The layout of the 256-thread launches whose LQ matrix does not fit LDS
-    (input site and LQ matrix in the work-group's scratch; with FP32
-    factorisations the explicit Q stages one reflector at a time through LDS)
+    (the LQ matrix in the work-group's scratch; with FP32 factorisations the
+    explicit Q stages one reflector at a time through LDS)
     gives the same log Z, bit for bit, as the LDS layout: the same operations in
     the same order per row.  d = 3, exact (two columns per site) and truncated."""
     d = 3

@@ -412,15 +412,25 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
       bool staged = false;
       if constexpr (XG && sizeof(Fac) == 4) {
         // X in global scratch (FP32 factorisations: the plans that need it):
-        // the reflectors are staged through LDS and the rows of Q written
-        // straight to the site region
+        // the reflectors are staged through LDS in chunks and the rows of Q
+        // written straight to the site region.  The chunks use the LDS of the
+        // input site's copy and of T, both dead by now (L, the next site's
+        // carry, comes after them); at least the two rows of vtmp.
         if (lq_regs_fit<Fac>(mJ, nn)) {
+          const int W = nn <= 128 ? 128 : 256;
+          uint8_t* b0 = reinterpret_cast<uint8_t*>(Aj ? Aj : T);
+          Fac* buf = reinterpret_cast<Fac*>(b0);
+          int cap = (int)((reinterpret_cast<uint8_t*>(L) - b0) / (W * (int)sizeof(Fac)));
+          if (cap < 2) {
+            buf = vtmp;
+            cap = 2;
+          }
           if (nn <= 128)
             lq_form_q_staged<Fac, Real, 8>((const glb_t<Fac>*)X, mJ, nn, nn, (const lds_t<Fac>*)tau,
-                                           (lds_t<Fac>*)vtmp, (glb_t<Real>*)g, nn);
+                                           (lds_t<Fac>*)buf, cap, (glb_t<Real>*)g, nn);
           else
             lq_form_q_staged<Fac, Real, 16>((const glb_t<Fac>*)X, mJ, nn, nn, (const lds_t<Fac>*)tau,
-                                            (lds_t<Fac>*)vtmp, (glb_t<Real>*)g, nn);
+                                            (lds_t<Fac>*)buf, cap, (glb_t<Real>*)g, nn);
           staged = true;
         }
       }

@@ -614,77 +614,63 @@ __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
 
 // Explicit Q as lq_form_q_regs, for reflectors kept outside LDS (the LQ
 // matrix in the work-group's global scratch, lq_factor output as is: L below
-// the diagonal).  The reflectors go through LDS one at a time, in the order
-// every row applies them (k-1 down to 0), and each lane group applies the
-// staged one to all of its rows, so X is read once instead of once per row.
-// Row r starts as e_r - tau_r v_r at step r and takes reflectors r-1..0 after
-// it: per row, the operations and their order are those of lq_form_q_regs.
-// One barrier per reflector; the next one is loaded while the current one is
-// applied and lands in the other half of vb (32 NPL elements of LDS).  Rows
-// 0..k-1 of Q go to out (leading dimension ldo).  Out of line: inlined into
-// the sweep, its four live row slots push the 256-thread build past the
-// registers of two waves per SIMD.
+// the diagonal).  The reflectors go through LDS in chunks of up to cap (buf:
+// cap x 16 NPL elements of LDS), from k-1 down; within a chunk each lane group
+// takes its rows through the chunk's reflectors with no barrier, as
+// lq_form_q_regs does with all of them.  Row r starts as e_r - tau_r v_r in the
+// chunk that holds reflector r and takes reflectors r-1..0 after it: per row,
+// the operations and their order are those of lq_form_q_regs.  Two barriers
+// per chunk.  Rows 0..k-1 of Q go to out (leading dimension ldo).  Out of
+// line: inlined into the sweep, its four live row slots push the 256-thread
+// build past the registers of two waves per SIMD.
 template <typename Fac, typename Out, int NPL>
 __device__ __attribute__((noinline)) void lq_form_q_staged(const glb_t<Fac>* X, int m, int n, int ld,
-                                                           const lds_t<Fac>* tau, lds_t<Fac>* vb, glb_t<Out>* out,
-                                                           int ldo) {
+                                                           const lds_t<Fac>* tau, lds_t<Fac>* buf, int cap,
+                                                           glb_t<Out>* out, int ldo) {
   constexpr int RPG = lq_rpg<Fac>();
   constexpr int NG = NT / 16;
-  constexpr int W = 16 * NPL;               // staged row: columns 0..W-1, zeros past n
-  constexpr int PER = (W + NT - 1) / NT;    // staged elements per thread
+  constexpr int W = 16 * NPL;  // staged row: columns 0..W-1, zeros past n
   const int k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
-  if (k == 0) return;
-  // reflector i as a full row: zeros left of i, the implicit one, the tail
-  auto fetch = [&](int i, int c) -> Fac {
-    return c < i ? Fac(0) : (c == i ? Fac(1) : (c < n ? X[i * ld + c] : Fac(0)));
-  };
-#pragma unroll
-  for (int s = 0; s < PER; ++s) {
-    const int c = tid + s * NT;
-    if (c < W) vb[((k - 1) & 1) * W + c] = fetch(k - 1, c);
-  }
-  __syncthreads();
   Fac q[RPG][NPL];
 #pragma unroll
   for (int j = 0; j < RPG; ++j)
 #pragma unroll
     for (int c = 0; c < NPL; ++c) q[j][c] = Fac(0);
-  for (int i = k - 1; i >= 0; --i) {
-    Fac pre[PER];
-#pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int c = tid + s * NT;
-      pre[s] = (i > 0 && c < W) ? fetch(i - 1, c) : Fac(0);
+  for (int hi = k - 1; hi >= 0; hi -= cap) {
+    const int lo = hi - cap + 1 > 0 ? hi - cap + 1 : 0;
+    // reflectors lo..hi as full rows: zeros left of i, the implicit one, the tail
+    for (int e = tid; e < (hi - lo + 1) * W; e += NT) {
+      const int i = lo + e / W, c = e % W;
+      buf[e] = c < i ? Fac(0) : (c == i ? Fac(1) : (c < n ? X[i * ld + c] : Fac(0)));
     }
-    const lds_t<Fac>* v = vb + (i & 1) * W + lane;
-    const Fac t = tau[i];
-    // one register copy of the staged row serves all row slots (reading it per
-    // slot and per use would make the step LDS-bound)
-    Fac vv[NPL];
-#pragma unroll
-    for (int c = 0; c < NPL; ++c) vv[c] = v[16 * c];
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < RPG; ++j) {
       const int r = lq_q_row(j, grp, NG);
-      if (r == i) {
+      if (r >= k || r < lo) continue;  // a row below the chunk starts in a later one
+      int i = hi;
+      if (r <= hi) {
+        const Fac t = tau[r];
+        const lds_t<Fac>* v = buf + (r - lo) * W + lane;
 #pragma unroll
-        for (int c = 0; c < NPL; ++c) q[j][c] = (lane + 16 * c == r ? Fac(1) : Fac(0)) - t * vv[c];
-      } else if (r > i && r < k) {
+        for (int c = 0; c < NPL; ++c) q[j][c] = (lane + 16 * c == r ? Fac(1) : Fac(0)) - t * v[16 * c];
+        i = r - 1;
+      }
+      for (; i >= lo; --i) {
+        const Fac t = tau[i];  // tau = 0 (no reflection) leaves q as it is
+        const lds_t<Fac>* v = buf + (i - lo) * W + lane;
+        Fac vv[NPL];
         Fac dp[4] = {Fac(0), Fac(0), Fac(0), Fac(0)};
 #pragma unroll
-        for (int c = 0; c < NPL; ++c) dp[c & 3] += q[j][c] * vv[c];
+        for (int c = 0; c < NPL; ++c) {
+          vv[c] = v[16 * c];
+          dp[c & 3] += q[j][c] * vv[c];
+        }
         const Fac dot = group_sum((dp[0] + dp[1]) + (dp[2] + dp[3]), 16);
         const Fac w = Fac(dot) * t;
 #pragma unroll
         for (int c = 0; c < NPL; ++c) q[j][c] -= w * vv[c];
-      }
-    }
-    if (i > 0) {
-#pragma unroll
-      for (int s = 0; s < PER; ++s) {
-        const int c = tid + s * NT;
-        if (c < W) vb[((i - 1) & 1) * W + c] = pre[s];
       }
     }
     __syncthreads();

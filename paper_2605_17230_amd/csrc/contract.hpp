@@ -390,7 +390,7 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
         }
         __syncthreads();
       }
-      lq_factor_any<Fac>(X, mJ, nn, nn, tau, diag, dred, vtmp);
+      lq_factor_any<Fac, XG>(X, mJ, nn, nn, tau, diag, dred, vtmp);
       // L (mJ x k) for the site to the left
       auto lval = [&](int r, int c) { return c < r ? X[r * nn + c] : (c == r ? diag[r] : Fac(0)); };
       if (PL && J > 0) {

@@ -11,6 +11,8 @@
 #endif
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "plan.hpp"
 
 namespace tnmld {
@@ -315,7 +317,8 @@ __device__ inline void gemm_mfma_planes(int M, int N, int K, const uint16_t* Ah,
 // the other groups are still applying the current one to the rows below; the
 // FP64 tau of step i is handed over in red[i & 1].
 template <typename Real>
-__device__ void lq_factor(Real* X, int m, int n, int ld, Real* tau, Real* diag, double* red) {
+__device__ __attribute__((noinline)) void lq_factor(Real* X, int m, int n, int ld, Real* tau, Real* diag,
+                                                   double* red) {
   const int k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
   constexpr int NG = NT / 16;
@@ -390,7 +393,7 @@ __device__ void lq_factor(Real* X, int m, int n, int ld, Real* tau, Real* diag, 
 // (the reflector of step i is staged in v + (i & 1) * n one step ahead, so a
 // step needs a single barrier).
 template <typename Real>
-__device__ void lq_form_q(Real* X, int m, int n, int ld, const Real* tau, Real* v) {
+__device__ __attribute__((noinline)) void lq_form_q(Real* X, int m, int n, int ld, const Real* tau, Real* v) {
   const int k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
   if (k == 0) return;
@@ -457,9 +460,13 @@ __device__ inline int lq_q_row(int j, int g, int ng) {
 }
 
 // NPL: columns per lane held in registers (n <= 16 NPL); instantiated for 8
-// and 16 so that 128-column matrices do not run 256-column loops.
-template <typename Real, int NPL = LQR_NPL>
-__device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* diag, double* red, Real* vb) {
+// and 16 so that 128-column matrices do not run 256-column loops.  XT: the
+// element type of X with its address space (LDS, or global scratch); the other
+// buffers are LDS.  Out of line, with typed pointers so that LDS accesses stay
+// DS instructions.
+template <typename Real, int NPL, typename XT>
+__device__ __attribute__((noinline)) void lq_factor_regs(XT* X, int m, int n, int ld, lds_t<Real>* tau,
+                                                        lds_t<Real>* diag, lds_t<double>* red, lds_t<Real>* vb) {
   constexpr int LQR_RPG = lq_rpg<Real>();
   const int k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
@@ -497,7 +504,7 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
       sd = 1.0 / (x0 - beta);
     }
     const Real t = Real(td), scale = Real(sd);
-    Real* v = vb + (i & 1) * (16 * NPL);
+    lds_t<Real>* v = vb + (i & 1) * (16 * NPL);
 #pragma unroll
     for (int c = 0; c < NPL; ++c) {
       const int col = lane + 16 * c;
@@ -514,7 +521,7 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
   __syncthreads();
   for (int i = 0; i < k; ++i) {
     const Real t = Real(red[i & 1]);
-    const Real* v = vb + (i & 1) * (16 * NPL);
+    const lds_t<Real>* v = vb + (i & 1) * (16 * NPL);
     Real vv[NPL];
 #pragma unroll
     for (int c = 0; c < NPL; ++c) vv[c] = v[lane + 16 * c];  // staged with its zeros: no bounds test
@@ -557,7 +564,8 @@ __device__ void lq_factor_regs(Real* X, int m, int n, int ld, Real* tau, Real* d
 // index tests; FULL (n == 16 NPL) drops the bounds test on the columns too.
 // One barrier before the rows are stored.
 template <typename Real, int NPL, bool FULL>
-__device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
+__device__ __attribute__((noinline)) void lq_form_q_regs(lds_t<Real>* X, int m, int n, int ld,
+                                                        const lds_t<Real>* tau) {
   constexpr int LQR_RPG = lq_rpg<Real>();
   const int k = m < n ? m : n;
   const int tid = threadIdx.x, lane = tid & 15, grp = tid >> 4;
@@ -573,7 +581,7 @@ __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
     if (r >= k) continue;
     {
       const Real t = tau[r];
-      const Real* xr = X + r * ld;
+      const lds_t<Real>* xr = X + r * ld;
 #pragma unroll
       for (int c = 0; c < NPL; ++c) {
         const int col = lane + 16 * c;
@@ -583,7 +591,7 @@ __device__ void lq_form_q_regs(Real* X, int m, int n, int ld, const Real* tau) {
     }
     for (int i = r - 1; i >= 0; --i) {
       const Real t = tau[i];  // tau = 0 (no reflection) leaves q as it is
-      const Real* xi = X + i * ld;
+      const lds_t<Real>* xi = X + i * ld;
       Real vv[NPL];
       Real dp[4] = {Real(0), Real(0), Real(0), Real(0)};
 #pragma unroll
@@ -687,22 +695,33 @@ __device__ __attribute__((noinline)) void lq_form_q_staged(const glb_t<Fac>* X, 
 }
 
 // Dispatch: registers when the matrix fits, else the LDS-resident version.
-template <typename Real>
-__device__ inline void lq_factor_any(Real* X, int m, int n, int ld, Real* tau, Real* diag, double* red, Real* vb) {
+// tau, diag, red and vb are LDS; X is LDS, or global scratch when XGL.
+template <typename Real, bool XGL = false>
+__device__ inline __attribute__((always_inline)) void lq_factor_any(Real* X, int m, int n, int ld, Real* tau,
+                                                                    Real* diag, double* red, Real* vb) {
+  using XT = typename std::conditional<XGL, glb_t<Real>, lds_t<Real>>::type;
   if (lq_regs_fit<Real>(m, n)) {
-    if (n <= 128) lq_factor_regs<Real, 8>(X, m, n, ld, tau, diag, red, vb);
-    else lq_factor_regs<Real, 16>(X, m, n, ld, tau, diag, red, vb);
+    auto tl = (lds_t<Real>*)tau;
+    auto dl = (lds_t<Real>*)diag;
+    auto rl = (lds_t<double>*)red;
+    auto vl = (lds_t<Real>*)vb;
+    if (n <= 128) lq_factor_regs<Real, 8, XT>((XT*)X, m, n, ld, tl, dl, rl, vl);
+    else lq_factor_regs<Real, 16, XT>((XT*)X, m, n, ld, tl, dl, rl, vl);
   } else {
     lq_factor<Real>(X, m, n, ld, tau, diag, red);
   }
 }
+// X and tau are LDS.
 template <typename Real>
-__device__ inline void lq_form_q_any(Real* X, int m, int n, int ld, const Real* tau, Real* v) {
+__device__ inline __attribute__((always_inline)) void lq_form_q_any(Real* X, int m, int n, int ld, const Real* tau,
+                                                                    Real* v) {
   if (lq_regs_fit<Real>(m, n)) {
-    if (n == 128) lq_form_q_regs<Real, 8, true>(X, m, n, ld, tau);
-    else if (n == 256) lq_form_q_regs<Real, 16, true>(X, m, n, ld, tau);
-    else if (n < 128) lq_form_q_regs<Real, 8, false>(X, m, n, ld, tau);
-    else lq_form_q_regs<Real, 16, false>(X, m, n, ld, tau);
+    auto xl = (lds_t<Real>*)X;
+    auto tl = (const lds_t<Real>*)tau;
+    if (n == 128) lq_form_q_regs<Real, 8, true>(xl, m, n, ld, tl);
+    else if (n == 256) lq_form_q_regs<Real, 16, true>(xl, m, n, ld, tl);
+    else if (n < 128) lq_form_q_regs<Real, 8, false>(xl, m, n, ld, tl);
+    else lq_form_q_regs<Real, 16, false>(xl, m, n, ld, tl);
   } else {
     lq_form_q<Real>(X, m, n, ld, tau, v);
   }
@@ -729,8 +748,9 @@ __device__ inline void lq_form_q_any(Real* X, int m, int n, int ld, const Real* 
 // eps: rounding unit of the data (of the storage type, which may be coarser
 // than Real).  lst: int scratch of cols entries.  Returns the number of sweeps.
 template <typename Real>
-__device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv, double tol, double eps, int* flag,
-                          double* red, double* nrm, int* lst) {
+__device__ __attribute__((noinline)) int jacobi_svd_lds(lds_t<Real>* M, int rows, int cols, int ldm, lds_t<Real>* V,
+                                                        int ldv, double tol, double eps, lds_t<int>* flag,
+                                                        lds_t<double>* red, lds_t<double>* nrm, lds_t<int>* lst) {
   constexpr int MAXR = 4;  // rows (and V rows) lane + j G, j < MAXR, live in registers; the rest stream from LDS
   if (cols < 2) return 0;
   const int tid = threadIdx.x;
@@ -803,8 +823,8 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
       }
       const bool act = g < P && q < nlive;
       const int cp = act ? lst[p] : 0, cq = act ? lst[q] : 0;
-      Real* a = M + cp * ldm;
-      Real* b = M + cq * ldm;
+      lds_t<Real>* a = M + cp * ldm;
+      lds_t<Real>* b = M + cq * ldm;
       Real xa[MAXR], xb[MAXR];
       double gp[2] = {0.0, 0.0};  // FP64 sums: no underflow of small columns
 #pragma unroll
@@ -820,8 +840,8 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
       if (act)
         for (int r = lane + MAXR * G; r < rows; r += G) gp[0] += (double)a[r] * (double)b[r];
       // the rotation's V columns are loaded now so that their latency overlaps the reduction
-      Real* va = V + cp * ldv;
-      Real* vb = V + cq * ldv;
+      lds_t<Real>* va = V + cp * ldv;
+      lds_t<Real>* vb = V + cq * ldv;
       Real ya[MAXR], yb[MAXR];
 #pragma unroll
       for (int j = 0; j < MAXR; ++j) {
@@ -898,6 +918,15 @@ __device__ int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V, int ldv
     if (!f) return sweep + 1;
   }
   return sweep;
+}
+
+// jacobi_svd_lds on buffers that are all in LDS (the caller's pointers).
+template <typename Real>
+__device__ inline __attribute__((always_inline)) int jacobi_svd(Real* M, int rows, int cols, int ldm, Real* V,
+                                                                int ldv, double tol, double eps, int* flag,
+                                                                double* red, double* nrm, int* lst) {
+  return jacobi_svd_lds<Real>((lds_t<Real>*)M, rows, cols, ldm, (lds_t<Real>*)V, ldv, tol, eps, (lds_t<int>*)flag,
+                              (lds_t<double>*)red, (lds_t<double>*)nrm, (lds_t<int>*)lst);
 }
 
 

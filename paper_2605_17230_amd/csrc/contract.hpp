@@ -296,11 +296,16 @@ template <typename Real, typename Fac, int GM, bool XG = false>
 __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, const double* rates, Real* scr,
                          const int64_t* region, Work<Real, Fac>& w, double& logscale) {
   const int tid = threadIdx.x;
-  uint8_t* fbits = w.fbits;
-  int* perm = w.perm;
-  double* dred = w.dred;
-  Real *Wv = w.Wv, *Aj = w.Aj, *T = w.T, *L = w.L, *C = w.C;
-  Fac *X = w.X, *tau = w.tau, *diag = w.diag, *vtmp = w.vtmp, *Mm = w.Mm, *Vv = w.Vv, *Lt = w.Lt, *sig = w.sig;
+  // the work areas are LDS (X global scratch when XG): said explicitly, so that
+  // an out-of-line copy (the adjoint's) keeps DS instructions for them
+  uint8_t* fbits = in_lds(w.fbits);
+  int* perm = in_lds(w.perm);
+  double* dred = in_lds(w.dred);
+  Real *Wv = in_lds(w.Wv), *Aj = w.Aj ? in_lds(w.Aj) : nullptr, *T = in_lds(w.T), *L = in_lds(w.L),
+       *C = in_lds(w.C);
+  Fac *X = XG ? in_global(w.X) : in_lds(w.X), *tau = in_lds(w.tau), *diag = in_lds(w.diag), *vtmp = in_lds(w.vtmp),
+      *Mm = in_lds(w.Mm), *Vv = in_lds(w.Vv), *Lt = in_lds(w.Lt), *sig = in_lds(w.sig);
+  int* s_dead = in_lds(w.s_dead);
   // BF16 form: T and L reach the T.L GEMM as bf16 hi/lo planes, split once
   // when they are written (T row-major, L transposed; rows padded to 8)
 #ifndef TNMLD_EMU
@@ -308,7 +313,7 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
 #else
   constexpr bool PL = false;
 #endif
-  if (tid == 0) w.s_dead[0] = 0;
+  if (tid == 0) s_dead[0] = 0;
   __syncthreads();
   do {
     // --- right-to-left: MPO apply + LQ --------------------------------------
@@ -445,13 +450,13 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
       const Real l0 = L[0];
       __syncthreads();
       if (!(fabs((double)l0) > 0.0)) {
-        if (tid == 0) w.s_dead[0] = 1;
+        if (tid == 0) s_dead[0] = 1;
       } else {
         logscale += log(fabs((double)l0));
         if (tid == 0) C[0] = l0 > Real(0) ? Real(1) : Real(-1);
       }
       __syncthreads();
-      if (w.s_dead[0]) break;
+      if (s_dead[0]) break;
     }
     // --- left-to-right: QR of every site matrix, SVD where the bond is cut ----
     for (int J = 0; J < nsite; ++J) {
@@ -488,7 +493,7 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
           // last site: 1x1 carry = remaining norm (sign folded into the site)
           const double l0 = (double)Lt[0];
           if (!(fabs(l0) > TinyNorm<Fac>::v)) {
-            if (tid == 0) w.s_dead[0] = 1;
+            if (tid == 0) s_dead[0] = 1;
           } else {
             logscale += log(fabs(l0));
             if (l0 < 0.0)
@@ -502,7 +507,7 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
         for_2d(k2, k2, [&](int r, int c) { Vv[r * ldl + c] = r == c ? Fac(1) : Fac(0); });
         __syncthreads();
         // the data carry the rounding of the storage type Real, whatever Fac is
-        jacobi_svd<Fac>(Lt, kr, k2, ldl, Vv, ldl, SplitTol<Fac>::v, (double)Eps<Real>::v, w.s_flag, dred, w.nrm, perm);
+        jacobi_svd<Fac>(Lt, kr, k2, ldl, Vv, ldl, SplitTol<Fac>::v, (double)Eps<Real>::v, in_lds(w.s_flag), dred, in_lds(w.nrm), perm);
         for (int c = tid; c < k2; c += NT) {
           double s2 = 0;
           for (int r = 0; r < kr; ++r) s2 += (double)Lt[c * ldl + r] * (double)Lt[c * ldl + r];
@@ -540,10 +545,10 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
         for_2d(Dn, kr, [&](int r, int c) { C[r * kr + c] = Real(Lt[perm[r] * ldl + c]); });
         __syncthreads();
       }
-      if (w.s_dead[0]) break;
+      if (s_dead[0]) break;
     }
   } while (0);
-  const bool alive = !w.s_dead[0];
+  const bool alive = !s_dead[0];
   __syncthreads();
   return alive;
 }

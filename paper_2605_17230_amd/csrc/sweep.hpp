@@ -39,6 +39,22 @@ template <typename T>
 using glb_t = T;
 #endif
 
+// A generic pointer known to address LDS: the assumption lets the compiler use
+// DS instructions for it where it cannot trace the pointer back to LDS itself
+// (in out-of-line functions).  in_global: the same statement for global
+// memory, for the reader (no assumption is available).
+template <typename T>
+__device__ inline T* in_lds(T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_assume(__builtin_amdgcn_is_shared((const void*)p));
+#endif
+  return p;
+}
+template <typename T>
+__device__ inline T* in_global(T* p) {
+  return p;
+}
+
 template <typename Real>
 struct Eps;
 template <>

@@ -435,7 +435,9 @@ def bench_rounds(a, torch, tn, synth, dev, stream):
                    "precision": a.precision},
         "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": ach / PEAK_ALU_TFLOPS, "traffic": None, "flops_per_launch": flops,
-                     "kernel": "fwd_kernel"},
+                     # the two-round plan's 64-row site matrices fit the 256-thread build with FP32
+                     # factorisations only (LQ matrix in scratch); with FP64 ones the 512-thread build runs
+                     "kernel": "fwd_kernel_small" if a.precision in ("bf16", "fp32plain") else "fwd_kernel"},
         "logical_error_rate": float((cls != smp["true_class"]).mean()),
         "environment": environment(),
     }

@@ -188,7 +188,7 @@ struct Work {
   int* perm;
   double* dred;
   double* nrm;
-  Real *Wv, *Aj, *T, *L, *C;
+  Real *Wv, *Aj, *T, *T2, *L, *C;
   Fac *X, *tau, *diag, *vtmp, *Mm, *Vv, *Lt, *sig;
   int* s_flag;
   int* s_dead;
@@ -213,6 +213,7 @@ __device__ inline Work<Real, Fac> carve(uint8_t* smem, const LdsLayout& lay, int
   w.Wv = reinterpret_cast<Real*>(smem + lay.W);
   w.Aj = lay.Aj < 0 ? nullptr : reinterpret_cast<Real*>(smem + lay.Aj);
   w.T = reinterpret_cast<Real*>(smem + lay.T);
+  w.T2 = (XG && lay.T2 >= 0) ? reinterpret_cast<Real*>(smem + lay.T2) : nullptr;
   w.L = reinterpret_cast<Real*>(smem + lay.L);
   w.C = reinterpret_cast<Real*>(smem + lay.C);
   if constexpr (XG) w.X = reinterpret_cast<Fac*>(gbase + lay.xg);
@@ -302,7 +303,7 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
   int* perm = in_lds(w.perm);
   double* dred = in_lds(w.dred);
   Real *Wv = in_lds(w.Wv), *Aj = w.Aj ? in_lds(w.Aj) : nullptr, *T = in_lds(w.T), *L = in_lds(w.L),
-       *C = in_lds(w.C);
+       *C = in_lds(w.C), *T2 = (XG && w.T2) ? in_lds(w.T2) : nullptr;
   Fac *X = XG ? in_global(w.X) : in_lds(w.X), *tau = in_lds(w.tau), *diag = in_lds(w.diag), *vtmp = in_lds(w.vtmp),
       *Mm = in_lds(w.Mm), *Vv = in_lds(w.Vv), *Lt = in_lds(w.Lt), *sig = in_lds(w.sig);
   int* s_dead = in_lds(w.s_dead);
@@ -360,40 +361,82 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
       __syncthreads();
       const int ldp = (RB + 7) & ~7;  // plane row length (BF16 form)
       const int sA = A == 4 ? 2 : (A == 2 ? 1 : 0), sB = B == 4 ? 2 : (B == 2 ? 1 : 0);
-      for (int so = 0; so < qo; ++so) {
+      for (int so = 0; so < qo;) {
         // T[(l,a)][(r,b)] = sum_si Aj[l][si][r] W[a][si][so][b]
-        // (A and B, the MPO bonds, are 1, 2 or 4)
-        auto tval = [&](int la, int rb) {
+        // (A and B, the MPO bonds, are 1, 2 or 4); with a second T slice in
+        // LDS (the layouts with the LQ matrix in scratch have room for one),
+        // slices so and so + 1 in one pass, sharing the loads of Aj (each
+        // slice's sum is formed as when built alone)
+        const bool two = XG && T2 && so + 1 < qo;
+        auto tval = [&](int la, int rb, int s) {
           const int l = la >> sA, a = la & (A - 1), r = rb >> sB, bb = rb & (B - 1);
           Real acc = 0;
           for (int si = 0; si < qi; ++si)
-            acc += As[(l * qi + si) * Dr + r] * Wv[((a * qi + si) * qo + so) * B + bb];
+            acc += As[(l * qi + si) * Dr + r] * Wv[((a * qi + si) * qo + s) * B + bb];
           return acc;
+        };
+        auto tval2 = [&](int la, int rb, Real& v0, Real& v1) {
+          const int l = la >> sA, a = la & (A - 1), r = rb >> sB, bb = rb & (B - 1);
+          Real acc0 = 0, acc1 = 0;
+          for (int si = 0; si < qi; ++si) {
+            const Real x = As[(l * qi + si) * Dr + r];
+            acc0 += x * Wv[((a * qi + si) * qo + so) * B + bb];
+            acc1 += x * Wv[((a * qi + si) * qo + so + 1) * B + bb];
+          }
+          v0 = acc0;
+          v1 = acc1;
         };
         if constexpr (PL) {
 #ifndef TNMLD_EMU
           uint16_t* Th = reinterpret_cast<uint16_t*>(T);
           uint16_t* Tl = Th + mJ * ldp;
-          for_2d(mJ, ldp, [&](int la, int rb) {
-            uint16_t h, l;
-            split_bf16(rb < RB ? float(tval(la, rb)) : 0.0f, h, l);
-            Th[la * ldp + rb] = h;
-            Tl[la * ldp + rb] = l;
-          });
+          uint16_t* Th2 = reinterpret_cast<uint16_t*>(T2);
+          uint16_t* Tl2 = Th2 + mJ * ldp;
+          if (two) {
+            for_2d(mJ, ldp, [&](int la, int rb) {
+              Real v0 = Real(0), v1 = Real(0);
+              if (rb < RB) tval2(la, rb, v0, v1);
+              uint16_t h, l;
+              split_bf16(float(v0), h, l);
+              Th[la * ldp + rb] = h;
+              Tl[la * ldp + rb] = l;
+              split_bf16(float(v1), h, l);
+              Th2[la * ldp + rb] = h;
+              Tl2[la * ldp + rb] = l;
+            });
+          } else {
+            for_2d(mJ, ldp, [&](int la, int rb) {
+              uint16_t h, l;
+              split_bf16(rb < RB ? float(tval(la, rb, so)) : 0.0f, h, l);
+              Th[la * ldp + rb] = h;
+              Tl[la * ldp + rb] = l;
+            });
+          }
           __syncthreads();
           // X[:, so*kr + c] = T . L
           const uint16_t* Lh = reinterpret_cast<const uint16_t*>(L);
           gemm_mfma_planes(mJ, kr, RB, Th, Tl, ldp, Lh, Lh + kr * ldp, ldp,
                            [&](int i, int j, float v) { X[i * nn + so * kr + j] = Fac(v); });
+          if (two)
+            gemm_mfma_planes(mJ, kr, RB, Th2, Tl2, ldp, Lh, Lh + kr * ldp, ldp,
+                             [&](int i, int j, float v) { X[i * nn + (so + 1) * kr + j] = Fac(v); });
 #endif
         } else {
-          for_2d(mJ, RB, [&](int la, int rb) { T[la * RB + rb] = tval(la, rb); });
+          if (two) {
+            for_2d(mJ, RB, [&](int la, int rb) { tval2(la, rb, T[la * RB + rb], T2[la * RB + rb]); });
+          } else {
+            for_2d(mJ, RB, [&](int la, int rb) { T[la * RB + rb] = tval(la, rb, so); });
+          }
           __syncthreads();
           // X[:, so*kr + c] = T . L
           contract_gemm<GM, Real>(mJ, kr, RB, T, RB, L, kr, 0, 0,
                                   [&](int i, int j, Real v) { X[i * nn + so * kr + j] = Fac(v); });
+          if (two)
+            contract_gemm<GM, Real>(mJ, kr, RB, T2, RB, L, kr, 0, 0,
+                                    [&](int i, int j, Real v) { X[i * nn + (so + 1) * kr + j] = Fac(v); });
         }
         __syncthreads();
+        so += two ? 2 : 1;
       }
       lq_factor_any<Fac, XG>(X, mJ, nn, nn, tau, diag, dred, vtmp);
       // L (mJ x k) for the site to the left
@@ -507,7 +550,8 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
         for_2d(k2, k2, [&](int r, int c) { Vv[r * ldl + c] = r == c ? Fac(1) : Fac(0); });
         __syncthreads();
         // the data carry the rounding of the storage type Real, whatever Fac is
-        jacobi_svd<Fac>(Lt, kr, k2, ldl, Vv, ldl, SplitTol<Fac>::v, (double)Eps<Real>::v, in_lds(w.s_flag), dred, in_lds(w.nrm), perm);
+        jacobi_svd<Fac>(Lt, kr, k2, ldl, Vv, ldl, SplitTol<Fac>::v, (double)Eps<Real>::v, in_lds(w.s_flag), dred,
+                        in_lds(w.nrm), perm);
         for (int c = tid; c < k2; c += NT) {
           double s2 = 0;
           for (int r = 0; r < kr; ++r) s2 += (double)Lt[c * ldl + r] * (double)Lt[c * ldl + r];

@@ -136,6 +136,7 @@ void merge_maxima(PlanHeader* acc, const PlanHeader& h);
 // (C, M, V, Q, sig) are never live together and share storage.
 struct LdsLayout {
   int32_t Aj, T, X, L;                // right-to-left phase
+  int32_t T2;                         // a second slice of T where the phase has room for it, else -1
   int32_t C, M, V, Lt, Q, sig;        // left-to-right phase
   int32_t tau, diag, v;               // Householder scalars and reflector (both phases)
   int32_t W;                          // MPO values of the current site (<= 64, storage type)
@@ -183,6 +184,11 @@ inline LdsLayout lds_layout(const PlanHeader& h, int rb, int fb, bool aj_global 
   o.Lt = p; p += pad64b((int64_t)h.max_V * fb);
   o.sig = p; p += pad64b((int64_t)(h.max_kr > h.max_bond ? h.max_kr : h.max_bond) * fb);
   const int32_t lr_end = p;
+  // a second T slice (the MPO step then builds two output slices per pass) where
+  // the right-to-left phase has room for it below the left-to-right phase's end
+  // (used by the kernels built for an LQ matrix in scratch)
+  o.T2 = -1;
+  if (rl_end + pad64b((int64_t)h.max_T * rb) <= lr_end) o.T2 = rl_end;
   p = rl_end > lr_end ? rl_end : lr_end;
   const int32_t nh = h.max_m > h.max_kr ? h.max_m : h.max_kr;
   int32_t nv = h.max_n > h.max_rows ? h.max_n : h.max_rows;

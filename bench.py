@@ -118,7 +118,7 @@ def cpu_baseline(d, rates, syn, target_s, min_count=256):
     return ref, n, dt, threads
 
 
-DTYPE = {"fp32plain": "f32", "fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32"}
+DTYPE = {"fp32plain": "f32", "fp32": "f32+f64", "fp64": "f64", "bf16": "bf16+f32", "bf16f64": "bf16+f64"}
 
 
 def max_finite_diff(a, b):
@@ -169,7 +169,7 @@ def measured_traffic(precision, count, workload):
 def bench_adjoint(a, torch, tn, synth, dev, stream):
     """Forward + backward of sum_b log P(s_b) over the gradient workload."""
     s = synth.config_inputs("C5")[0]
-    prec = a.precision if a.precision != "bf16" else "fp32"
+    prec = "fp32" if a.precision in ("bf16", "bf16f64") else a.precision  # the adjoint's forms
     n = len(s["syndromes"])
     seg = tn.SegmentInput(s["d"], s["chi"], torch.from_numpy(s["syndromes"]).to(dev),
                           torch.from_numpy(s["rates"]).to(dev), None, prec)
@@ -227,7 +227,7 @@ def bench_fit(a, torch, tn, synth, dev):
     error rate of decoding fresh syndromes of the same model with the true,
     the refitted (largest N) and the starting prior."""
     s = synth.config_inputs("C5")[0]
-    prec = a.precision if a.precision != "bf16" else "fp32"
+    prec = "fp32" if a.precision in ("bf16", "bf16f64") else a.precision  # the adjoint's forms
     d, chi = s["d"], s["chi"]
     syn_all = torch.from_numpy(s["syndromes"]).to(dev)
     true_rates = s["rates"][0]
@@ -398,7 +398,7 @@ def bench_rounds(a, torch, tn, synth, dev, stream):
     on a sample."""
     import oracle
     d, p, q, T, n = 7, 0.02, 0.02, 2, a.count
-    chi = 12 if a.precision in ("fp64", "fp32") else 16
+    chi = 12 if a.precision in ("fp64", "fp32", "bf16f64") else 16
     rates = synth.depolarizing(d, p)
     meas = np.full(d * d - 1, q)
     smp = synth.sample_phenom(d, rates, meas, T, n, 7000)
@@ -568,13 +568,15 @@ def main():
         "launch": {"%d:%d" % k: {"group": v[0], "wg_per_cu": v[1], "threads": v[2]} for k, v in shapes.items()},
         "wall_s": wall,
     }
-    if a.precision == "bf16":
-        # the GEMM-class part on the matrix cores: each product runs as three
-        # bf16 MFMA products (hi/lo split), counted once here
+    if a.precision in ("bf16", "bf16f64"):
+        # the GEMM-class part on the matrix cores, counted once: in the split
+        # form each product runs as three bf16 MFMA products (hi/lo), in the
+        # single-rounded form as one
         mf = gemm_per_step / (ms_step / 1e3) / 1e12
         out["mfma"] = {"gemm_flops_per_launch": gemm_per_step, "gemm_share_of_counted": gemm_per_step / flops_per_step,
                        "achieved": mf, "peak": PEAK_MFMA_BF16_TFLOPS, "unit": "TFLOP/s",
-                       "frac": mf / PEAK_MFMA_BF16_TFLOPS, "bf16_products_per_gemm_flop": 3}
+                       "frac": mf / PEAK_MFMA_BF16_TFLOPS,
+                       "bf16_products_per_gemm_flop": 3 if a.precision == "bf16" else 1}
     print("bench: timed %.1f ms per step" % ms_step, file=sys.stderr, flush=True)
     out["environment"] = environment()
     if a.workload == "c2":

@@ -90,9 +90,16 @@ typedef enum {
                         vectors) on bf16 MFMA with FP32 accumulation, operands
                         split into bf16 high and low parts; factorisations in
                         FP32 */
-  TN_FP32_PLAIN = 3  /* every contraction and factorisation in FP32 (norms and
+  TN_FP32_PLAIN = 3, /* every contraction and factorisation in FP32 (norms and
                         Jacobi inner products accumulate in FP64); the plain
                         single-precision form */
+  TN_BF16_F64 = 4    /* MPS stored in FP32; the same contraction GEMMs as
+                        TN_BF16 on bf16 MFMA with FP32 accumulation, operands
+                        rounded once to bf16 (no high/low split); the LQ, QR and
+                        SVD of the truncation in FP64 (Sec. 3.2.1 boundary MPS
+                        with BF16 contractions and an FP64 truncation step).
+                        Forward only: tn_coset_loglik_backward rejects it with
+                        TN_EUNSUPPORTED */
 } tn_precision;
 /* Log-scales, log Z, log P(s) and the class decision are FP64 in every form. */
 

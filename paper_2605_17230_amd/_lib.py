@@ -15,8 +15,8 @@ LIB_PATH = os.path.join(HERE, "libtnmld.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "tnmld.h")
 
 TN_OK, TN_EINVAL, TN_ENOMEM, TN_EDEVICE, TN_EUNSUPPORTED, TN_ENUMERIC = 0, -1, -2, -3, -4, -5
-TN_FP64, TN_FP32, TN_BF16, TN_FP32_PLAIN = 0, 1, 2, 3
-PRECISIONS = {"fp64": TN_FP64, "fp32": TN_FP32, "bf16": TN_BF16, "fp32plain": TN_FP32_PLAIN}
+TN_FP64, TN_FP32, TN_BF16, TN_FP32_PLAIN, TN_BF16_F64 = 0, 1, 2, 3, 4
+PRECISIONS = {"fp64": TN_FP64, "fp32": TN_FP32, "bf16": TN_BF16, "fp32plain": TN_FP32_PLAIN, "bf16f64": TN_BF16_F64}
 TN_MAX_SEGMENTS = 16
 TN_MAX_ROUNDS = 2
 

@@ -307,13 +307,15 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
   Fac *X = XG ? in_global(w.X) : in_lds(w.X), *tau = in_lds(w.tau), *diag = in_lds(w.diag), *vtmp = in_lds(w.vtmp),
       *Mm = in_lds(w.Mm), *Vv = in_lds(w.Vv), *Lt = in_lds(w.Lt), *sig = in_lds(w.sig);
   int* s_dead = in_lds(w.s_dead);
-  // BF16 form: T and L reach the T.L GEMM as bf16 hi/lo planes, split once
-  // when they are written (T row-major, L transposed; rows padded to 8)
+  // BF16 forms: T and L reach the T.L GEMM as bf16 planes, rounded (and, for
+  // the split form, split into hi/lo) once when they are written (T row-major,
+  // L transposed; rows padded to 8)
 #ifndef TNMLD_EMU
   constexpr bool PL = GM != GEMM_VALU && sizeof(Real) == 4;
 #else
   constexpr bool PL = false;
 #endif
+  constexpr bool SPL = GM == GEMM_BF16X3;  // the low planes are written and read
   if (tid == 0) s_dead[0] = 0;
   __syncthreads();
   do {
@@ -399,26 +401,26 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
               uint16_t h, l;
               split_bf16(float(v0), h, l);
               Th[la * ldp + rb] = h;
-              Tl[la * ldp + rb] = l;
+              if constexpr (SPL) Tl[la * ldp + rb] = l;
               split_bf16(float(v1), h, l);
               Th2[la * ldp + rb] = h;
-              Tl2[la * ldp + rb] = l;
+              if constexpr (SPL) Tl2[la * ldp + rb] = l;
             });
           } else {
             for_2d(mJ, ldp, [&](int la, int rb) {
               uint16_t h, l;
               split_bf16(rb < RB ? float(tval(la, rb, so)) : 0.0f, h, l);
               Th[la * ldp + rb] = h;
-              Tl[la * ldp + rb] = l;
+              if constexpr (SPL) Tl[la * ldp + rb] = l;
             });
           }
           __syncthreads();
           // X[:, so*kr + c] = T . L
           const uint16_t* Lh = reinterpret_cast<const uint16_t*>(L);
-          gemm_mfma_planes(mJ, kr, RB, Th, Tl, ldp, Lh, Lh + kr * ldp, ldp,
+          gemm_mfma_planes<GM == GEMM_BF16X3>(mJ, kr, RB, Th, Tl, ldp, Lh, Lh + kr * ldp, ldp,
                            [&](int i, int j, float v) { X[i * nn + so * kr + j] = Fac(v); });
           if (two)
-            gemm_mfma_planes(mJ, kr, RB, Th2, Tl2, ldp, Lh, Lh + kr * ldp, ldp,
+            gemm_mfma_planes<GM == GEMM_BF16X3>(mJ, kr, RB, Th2, Tl2, ldp, Lh, Lh + kr * ldp, ldp,
                              [&](int i, int j, float v) { X[i * nn + (so + 1) * kr + j] = Fac(v); });
 #endif
         } else {
@@ -450,7 +452,7 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
           uint16_t h, l;
           split_bf16(r < mJ ? float(lval(r, c)) : 0.0f, h, l);
           Lh[c * ldw + r] = h;
-          Lh[k * ldw + c * ldw + r] = l;
+          if constexpr (SPL) Lh[k * ldw + c * ldw + r] = l;
         });
 #endif
       } else {

@@ -289,8 +289,10 @@ __device__ inline bf16x8_t load_bf16x8(const uint16_t* p, bool ok) {
 // stored transposed (row c of Bh, Bl holds column c of B, leading dimension
 // ldb).  lda and ldb are multiples of 8, the planes 16-byte aligned, and
 // columns K..pad8(K)-1 of both hold zeros.  Same three products and lane
-// layout as gemm_mfma_bf16, with one 16-byte load per operand and k-step.
-template <typename Store>
+// layout as gemm_mfma_bf16, with one 16-byte load per operand and k-step;
+// without SPLIT only the high planes are read (one product: operands rounded
+// once to bf16).
+template <bool SPLIT = true, typename Store>
 __device__ inline void gemm_mfma_planes(int M, int N, int K, const uint16_t* Ah, const uint16_t* Al, int lda,
                                         const uint16_t* Bh, const uint16_t* Bl, int ldb, Store store) {
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
@@ -303,11 +305,15 @@ __device__ inline void gemm_mfma_planes(int M, int N, int K, const uint16_t* Ah,
     for (int k0 = 0; k0 < K; k0 += 32) {
       const int kk = k0 + lk;
       const bool oka = r < M && kk < K8, okb = c < N && kk < K8;
-      const bf16x8_t ah = load_bf16x8(Ah + r * lda + kk, oka), al = load_bf16x8(Al + r * lda + kk, oka);
-      const bf16x8_t bh = load_bf16x8(Bh + c * ldb + kk, okb), bl = load_bf16x8(Bl + c * ldb + kk, okb);
+      const bf16x8_t ah = load_bf16x8(Ah + r * lda + kk, oka);
+      const bf16x8_t bh = load_bf16x8(Bh + c * ldb + kk, okb);
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+      if constexpr (SPLIT) {
+        const bf16x8_t al = load_bf16x8(Al + r * lda + kk, oka);
+        const bf16x8_t bl = load_bf16x8(Bl + c * ldb + kk, okb);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {

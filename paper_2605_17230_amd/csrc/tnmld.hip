@@ -200,7 +200,7 @@ int device_info(DevInfo* out) {
 int real_bytes(int precision) { return precision == TN_FP64 ? 8 : 4; }
 int fac_bytes(int precision) { return (precision == TN_FP32_PLAIN || precision == TN_BF16) ? 4 : 8; }
 bool precision_built(int precision) {
-  return precision >= TN_FP64 && precision <= TN_FP32_PLAIN;
+  return precision >= TN_FP64 && precision <= TN_BF16_F64;
 }
 
 // largest usable LDS per block on gfx950 when no device is queried
@@ -234,8 +234,10 @@ const void* fwd_kernel_of(int precision) {
   if (precision == TN_FP64) return reinterpret_cast<const void*>(fwd_kernel<double, double, GEMM_VALU>);
   if (precision == TN_FP32) return reinterpret_cast<const void*>(fwd_kernel<float, double, GEMM_VALU>);
   if (precision == TN_BF16) return reinterpret_cast<const void*>(fwd_kernel<float, float, BF16_GEMM_MODE>);
+  if (precision == TN_BF16_F64) return reinterpret_cast<const void*>(fwd_kernel<float, double, GEMM_BF16>);
   return reinterpret_cast<const void*>(fwd_kernel<float, float, GEMM_VALU>);
 }
+// (no adjoint for TN_BF16_F64: the backward planner rejects it before asking)
 const void* bwd_kernel_of(int precision) {
   if (precision == TN_FP64) return reinterpret_cast<const void*>(bwd_kernel<double, double, GEMM_VALU>);
   if (precision == TN_FP32) return reinterpret_cast<const void*>(bwd_kernel<float, double, GEMM_VALU>);
@@ -344,7 +346,7 @@ int validate(const tn_segment* segs, int32_t nseg) {
     const tn_segment& s = segs[i];
     if (s.d < 3 || s.d > TN_MAX_D || s.d % 2 == 0) return fail(TN_EINVAL, "d must be odd in [3, 31]");
     if (s.chi < 0) return fail(TN_EINVAL, "chi must be >= 0");
-    if (s.precision < TN_FP64 || s.precision > TN_FP32_PLAIN) return fail(TN_EINVAL, "bad precision");
+    if (s.precision < TN_FP64 || s.precision > TN_BF16_F64) return fail(TN_EINVAL, "bad precision");
     if (s.n_models < 1) return fail(TN_EINVAL, "n_models must be >= 1");
     if (s.count < 0) return fail(TN_EINVAL, "count must be >= 0");
     if (s.count > 0 && (!s.rates || !s.syndromes || !s.out_logz)) return fail(TN_EINVAL, "null pointer");
@@ -392,7 +394,7 @@ bool small_plan(const PlanHeader& h, int precision) {
   return tnmld_small::small_wgs_per_cu(precision, lb, xg) >= 2;
 }
 
-constexpr int kMaxLaunches = 2 * (TN_FP32_PLAIN + 1);  // one per precision and size class
+constexpr int kMaxLaunches = 2 * (TN_BF16_F64 + 1);  // one per precision and size class
 
 struct Launch {
   const Plan* host_plan[TN_MAX_SEGMENTS];  // plan of each job (host copy)
@@ -558,6 +560,7 @@ int enqueue_forward(std::vector<Launch>& launches, char* header, char* regions, 
     if (L.precision == TN_FP64) rc = launch_fwd<double, double, GEMM_VALU>(L, L.nwg, scr, counter, st);
     else if (L.precision == TN_FP32) rc = launch_fwd<float, double, GEMM_VALU>(L, L.nwg, scr, counter, st);
     else if (L.precision == TN_BF16) rc = launch_fwd<float, float, BF16_GEMM_MODE>(L, L.nwg, scr, counter, st);
+    else if (L.precision == TN_BF16_F64) rc = launch_fwd<float, double, GEMM_BF16>(L, L.nwg, scr, counter, st);
     else rc = launch_fwd<float, float, GEMM_VALU>(L, L.nwg, scr, counter, st);
     if (rc) return rc;
     ++li;
@@ -686,8 +689,11 @@ int plan_backward(const tn_segment* segs, int32_t nseg, BwdLayout* bl) {
   DevInfo di;
   int rc = validate(segs, nseg);
   if (rc) return rc;
-  for (int i = 0; i < nseg; ++i)
+  for (int i = 0; i < nseg; ++i) {
     if (segs[i].rounds > 1) return fail(TN_EUNSUPPORTED, "the gradient takes segments of one syndrome round");
+    if (segs[i].precision == TN_BF16_F64 && segs[i].count > 0)
+      return fail(TN_EUNSUPPORTED, "the gradient is not built for TN_BF16_F64");
+  }
   if ((rc = device_info(&di))) return rc;
   bl->hdr_bytes = kAlign;  // counters and the status word
   if ((rc = plan_launches(segs, nseg, std::min(di.lds_max, kLdsLimit), &launches, &fwd, &nwgf, false))) return rc;
@@ -952,7 +958,7 @@ int tn_code_stabilizers(int32_t d, int32_t* type_out, int32_t* support_out) {
 }
 
 int tn_plan_adjoint_flops(int32_t d, int32_t chi, int32_t precision, double* out) {
-  if (!out || precision < TN_FP64 || precision > TN_FP32_PLAIN) return fail(TN_EINVAL, "bad arguments");
+  if (!out || precision < TN_FP64 || precision > TN_BF16_F64) return fail(TN_EINVAL, "bad arguments");
   Plan p;
   std::string why;
   if (choose_group(d, chi, precision, kLdsLimit, &p, &why) < 0) return fail(TN_EUNSUPPORTED, why);
@@ -963,7 +969,7 @@ int tn_plan_adjoint_flops(int32_t d, int32_t chi, int32_t precision, double* out
 }
 
 int tn_plan_gemm_flops(int32_t d, int32_t chi, int32_t precision, double* out) {
-  if (!out || precision < TN_FP64 || precision > TN_FP32_PLAIN) return fail(TN_EINVAL, "bad arguments");
+  if (!out || precision < TN_FP64 || precision > TN_BF16_F64) return fail(TN_EINVAL, "bad arguments");
   Plan p;
   std::string why;
   if (choose_group(d, chi, precision, kLdsLimit, &p, &why) < 0) return fail(TN_EUNSUPPORTED, why);
@@ -977,7 +983,7 @@ int tn_plan_info(int32_t d, int32_t chi, int32_t precision, double* info) {
 }
 
 int tn_plan_info_rounds(int32_t d, int32_t chi, int32_t precision, int32_t rounds, double* info) {
-  if (!info || precision < TN_FP64 || precision > TN_FP32_PLAIN || rounds < 0 || rounds > TN_MAX_ROUNDS)
+  if (!info || precision < TN_FP64 || precision > TN_BF16_F64 || rounds < 0 || rounds > TN_MAX_ROUNDS)
     return fail(TN_EINVAL, "bad arguments");
   if (rounds < 1) rounds = 1;
   Plan p;
@@ -1002,7 +1008,7 @@ int tn_plan_info_rounds(int32_t d, int32_t chi, int32_t precision, int32_t round
 
 int tn_set_tuning_ex(int32_t d, int32_t chi, int32_t precision, int32_t group, int32_t wg_per_cu,
                      int32_t threads) {
-  if (d < 3 || d > TN_MAX_D || d % 2 == 0 || chi < 0 || precision < TN_FP64 || precision > TN_FP32_PLAIN ||
+  if (d < 3 || d > TN_MAX_D || d % 2 == 0 || chi < 0 || precision < TN_FP64 || precision > TN_BF16_F64 ||
       group < 0 || group > 2 || wg_per_cu < 0 || wg_per_cu > 4 || (threads != 0 && threads != NT && threads != kSmallNT))
     return fail(TN_EINVAL, "bad tuning arguments");
   std::lock_guard<std::mutex> lk(g_mu);
@@ -1017,7 +1023,7 @@ int tn_set_tuning(int32_t d, int32_t chi, int32_t precision, int32_t group, int3
 }
 
 int tn_get_launch(int32_t d, int32_t chi, int32_t precision, int32_t* shape) {
-  if (!shape || precision < TN_FP64 || precision > TN_FP32_PLAIN) return fail(TN_EINVAL, "bad arguments");
+  if (!shape || precision < TN_FP64 || precision > TN_BF16_F64) return fail(TN_EINVAL, "bad arguments");
   // a one-segment call of this bucket: which build and how many groups per CU
   tn_segment sg{};
   sg.d = d;

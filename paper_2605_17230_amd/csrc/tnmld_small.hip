@@ -76,10 +76,12 @@ const void* kernel_of(int precision, bool xg = false) {
   if (precision == TN_FP64) return reinterpret_cast<const void*>(fwd_kernel_small<double, double, GEMM_VALU>);
   if (precision == TN_FP32) return reinterpret_cast<const void*>(fwd_kernel_small<float, double, GEMM_VALU>);
   if (precision == TN_BF16) return reinterpret_cast<const void*>(fwd_kernel_small<float, float, BF16_GEMM_MODE>);
+  if (precision == TN_BF16_F64) return reinterpret_cast<const void*>(fwd_kernel_small<float, double, GEMM_BF16>);
   return reinterpret_cast<const void*>(fwd_kernel_small<float, float, GEMM_VALU>);
 }
 
 const void* bwd_kernel_of(int precision) {
+  if (precision == TN_BF16_F64) return nullptr;  // forward only
   if (precision == TN_FP64) return reinterpret_cast<const void*>(bwd_kernel_small<double, double, GEMM_VALU>);
   if (precision == TN_FP32) return reinterpret_cast<const void*>(bwd_kernel_small<float, double, GEMM_VALU>);
   if (precision == TN_BF16) return reinterpret_cast<const void*>(bwd_kernel_small<float, float, BF16_GEMM_MODE>);
@@ -136,7 +138,7 @@ int launch_fwd_small(int precision, const void* jt, unsigned long long* counter,
 int small_bwd_wgs_per_cu(int precision, int lds_bytes) {
   const void* kern = bwd_kernel_of(precision);
   int nb = 0;
-  if (raise_lds(kern, lds_bytes) != 0 ||
+  if (!kern || raise_lds(kern, lds_bytes) != 0 ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, (size_t)lds_bytes) != hipSuccess)
     nb = 0;
   return nb;
@@ -146,7 +148,7 @@ int small_bwd_wgs_per_cu(int precision, int lds_bytes) {
 int launch_bwd_small(int precision, const void* jt, char* scratch, int64_t stride, const void* lay, int lds_bytes,
                      int flags, double* partials, int64_t pstride, int nwg, hipStream_t st) {
   const void* kern = bwd_kernel_of(precision);
-  if (raise_lds(kern, lds_bytes) != 0) return -1;
+  if (!kern || raise_lds(kern, lds_bytes) != 0) return -1;
   JobTable t = *reinterpret_cast<const JobTable*>(jt);
   LdsLayout l = *reinterpret_cast<const LdsLayout*>(lay);
   void* args[] = {&t, &scratch, &stride, &l, &flags, &partials, &pstride};

@@ -214,6 +214,21 @@ def test_gradient_rejects_repeated_rounds(L):
     assert rc == _lib.TN_EUNSUPPORTED
 
 
+def test_bf16_fp64_truncation_form(L):
+    """TN_BF16_F64 (single-rounded bf16 contraction GEMMs, FP64 truncation) is a
+    forward form: its plans build like the TN_FP32 form's (same storage and
+    factorisation types), and the gradient refuses it with TN_EUNSUPPORTED
+    before any device call."""
+    import paper_2605_17230_amd as tn
+    a, b = tn.plan_info(17, 32, "bf16f64"), tn.plan_info(17, 32, "fp32")
+    assert a["lds_bytes"] == b["lds_bytes"] and a["flops_syndrome"] == b["flops_syndrome"]
+    arr = (_lib.Segment * 1)(_seg(precision=_lib.TN_BF16_F64))
+    g = (ctypes.c_void_p * 1)(1)
+    assert L.tn_coset_loglik_backward(arr, 1, g, g, 0, None, 0, None) == _lib.TN_EUNSUPPORTED
+    arr = (_lib.Segment * 1)(_seg(precision=5))
+    assert L.tn_coset_loglik(arr, 1, None, 0, None) == _lib.TN_EINVAL
+
+
 @pytest.mark.parametrize("d,chi", [(5, 8), (11, 24), (17, 32)])
 def test_adjoint_flop_counts(d, chi):
     """tn_plan_adjoint_flops: the bottom-up sweep of a coset crosses the same

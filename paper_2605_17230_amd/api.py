@@ -418,11 +418,11 @@ class _LogPosterior(torch.autograd.Function):
     sweeps."""
 
     @staticmethod
-    def forward(ctx, log_rates, syndromes, model_index, d, chi, precision):
+    def forward(ctx, log_rates, syndromes, model_index, d, chi, precision, keep_states):
         rates = log_rates.detach().exp()
         seg = SegmentInput(d, chi, syndromes, rates, model_index, precision)
         ctx.states = None
-        if states_bytes([seg]) <= STATES_LIMIT_BYTES:
+        if keep_states and states_bytes([seg]) <= STATES_LIMIT_BYTES:
             outs, ctx.states = coset_loglik_save([seg])
             o = outs[0]
         else:
@@ -443,13 +443,15 @@ class _LogPosterior(torch.autograd.Function):
         else:
             _, grads = coset_loglik_backward([ctx.seg], [g_logp], outputs=[ctx.out])
         g = grads[0] if ctx.rates_dim == 3 else grads[0][0]
-        return g, None, None, None, None, None
+        return g, None, None, None, None, None, None
 
 
 def log_posterior(log_rates, syndromes, d, chi, precision="fp32", model_index=None):
     """(log P(s) [B], log Z [B, 4]) with autograd through log_rates
-    ([d*d, 3] or [M, d*d, 3] float64 = ln p_{q,X|Y|Z})."""
-    return _LogPosterior.apply(log_rates, syndromes, model_index, d, chi, precision)
+    ([d*d, 3] or [M, d*d, 3] float64 = ln p_{q,X|Y|Z}).  The forward keeps the
+    top sweep's states for the backward only when a gradient can follow."""
+    keep = torch.is_grad_enabled() and log_rates.requires_grad
+    return _LogPosterior.apply(log_rates, syndromes, model_index, d, chi, precision, keep)
 
 
 def _bitflip_rates(rates, n):

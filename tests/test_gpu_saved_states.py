@@ -57,6 +57,30 @@ def test_autograd_uses_saved_states():
     assert torch.equal(theta.grad, g[0][0])
 
 
+def test_no_states_kept_without_gradient():
+    """Under torch.no_grad (or for rates that need no gradient) log_posterior
+    runs the plain forward pass: same log P(s), and no state buffer is
+    allocated."""
+    tn = _tn()
+    d, chi = 7, 12
+    r = synth.inhomogeneous(d, 0.01, 0.1, seed=5)
+    smp = synth.sample(d, r, 24, seed=6)
+    syn = torch.from_numpy(smp["syndromes"]).to(DEV)
+    theta = torch.from_numpy(np.log(r)).to(DEV)
+    seg = tn.SegmentInput(d, chi, syn, theta.exp(), None, "fp32")
+    ref = tn.decode_segments([seg])[0].logp  # the workspace of this shape now exists
+    need = tn.states_bytes([seg])
+    torch.cuda.synchronize()
+    for grad_on, th in ((False, theta.clone().requires_grad_()), (True, theta)):
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        with torch.set_grad_enabled(grad_on):
+            logp, _ = tn.log_posterior(th, syn, d, chi, "fp32")
+        torch.cuda.synchronize()
+        assert torch.cuda.max_memory_allocated() - base < need // 2
+        assert torch.equal(logp.detach(), ref)
+
+
 def test_saved_call_argument_errors():
     tn = _tn()
     d = 5

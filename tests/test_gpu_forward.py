@@ -241,6 +241,44 @@ def test_truncated_d9_chi16_fp32(dev):
     assert (cls == rcls).mean() >= 0.99
 
 
+@pytest.mark.parametrize("d", [9, 13])
+@pytest.mark.parametrize("prec", ["bf16", "fp32plain"])
+def test_chi32_launch_shapes_vs_exact(dev, d, prec):
+    """chi = 32, two columns per site, at d = 9 and 13 under both launch
+    shapes: one 512-thread group per CU (LQ matrix in LDS) and two 256-thread
+    groups (LQ matrix in scratch, two T slices per pass, chunked reflector
+    staging; the tuned shape of these buckets).  Against the exact oracle with
+    the C3 bars of each form."""
+    import warnings
+    r = synth.depolarizing(d, 0.11)
+    smp = synth.sample(d, r, 64, seed=4000 + d)
+    ref = oracle.transfer(d, r, smp["syndromes"], threads=8)
+    fin = np.isfinite(ref)
+    post = np.where(fin, log_posterior(np.where(fin, ref, -np.inf)), -np.inf)
+    lp_ref, _ = oracle.decide(ref)
+    bar = C3_BARS[prec]
+    for shape in [(2, 1, 512), (2, 2, 256)]:
+        tn.set_tuning(d, 32, prec, *shape)
+        try:
+            assert tuple(tn.api.launch_shape(d, 32, prec)) == shape
+            with warnings.catch_warnings():
+                warnings.simplefilter("ignore", tn.api.UnresolvedCosetsWarning)
+                logz, logp, cls = run(dev, d, 32, prec, smp["syndromes"], r)
+        finally:
+            tn.set_tuning(d, 32, prec)  # back to the default, then the tuned shapes
+            tn.tune.load()
+        gfin = np.isfinite(logz)
+        assert not (gfin & ~fin).any()
+        assert post[fin & ~gfin].max(initial=-np.inf) < UNRESOLVED_POST
+        both = fin & gfin
+        e10 = float(np.abs(logz - ref)[both & (post >= -10)].max(initial=0))
+        e_lp = float(np.max(np.abs(logp - lp_ref)))
+        print("d=%d chi=32 %s %s: max |dlogP| %.3g, max |dlogZ| posterior >= e^-10 %.3g" % (d, prec, shape, e_lp, e10),
+              flush=True)
+        assert e_lp < bar["logp"] and e10 < bar["post10"]
+        check_classes(cls, ref, bar["logp"])
+
+
 def test_deterministic_and_segment_independent(dev):
     segs = []
     ins = []

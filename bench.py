@@ -132,9 +132,17 @@ def max_finite_diff(a, b):
     return m
 
 
-# Sources the boundary-MPS kernels (fwd_kernel, its 256-thread build, bwd_kernel)
+# Sources the boundary-MPS kernels (fwd_kernel, its two 256-thread builds, bwd_kernel)
 # are compiled from; the planar solver's files are not among them.
-FWD_SOURCES = ("adjoint.hpp", "contract.hpp", "plan.cpp", "plan.hpp", "sweep.hpp", "tnmld.hip", "tnmld_small.hip")
+FWD_SOURCES = ("adjoint.hpp", "contract.hpp", "plan.cpp", "plan.hpp", "sweep.hpp", "tnmld.hip", "tnmld_small.hip",
+               "tnmld_small3.hip")
+
+
+def kernel_name(shape):
+    """Forward kernel a launch shape (columns per site, groups per CU, threads) runs."""
+    if shape[2] != 256:
+        return "fwd_kernel"
+    return "fwd_kernel_small3" if shape[1] >= 3 else "fwd_kernel_small"
 
 
 def kernel_sources_sha256():
@@ -519,8 +527,12 @@ def main():
                         for s in segs_h)
     segs = inputs(a.precision)
     # the forward kernel build each distinct (d, chi) of the batch runs on
-    shapes = {(s["d"], s["chi"]): tn.api.launch_shape(s["d"], s["chi"], a.precision) for s in segs_h}
-    kernels = sorted({"fwd_kernel_small" if sh[2] == 256 else "fwd_kernel" for sh in shapes.values()})
+    shapes = {(s["d"], s["chi"]): tuple(tn.api.launch_shape(s["d"], s["chi"], a.precision)) for s in segs_h}
+    # one persistent launch per build: a call with plans on two 256-thread
+    # groups per CU runs its three-group plans there as well
+    if any(sh[2] == 256 and sh[1] < 3 for sh in shapes.values()):
+        shapes = {k: (sh[0], 2, 256) if sh[2] == 256 else sh for k, sh in shapes.items()}
+    kernels = sorted({kernel_name(sh) for sh in shapes.values()})
     print("bench: %s, %s, %d warmup + %d timed steps" % (workload, a.precision, a.warmup, a.steps),
           file=sys.stderr, flush=True)
     for _ in range(a.warmup):

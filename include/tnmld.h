@@ -256,6 +256,10 @@ int tn_set_tuning(int32_t d, int32_t chi, int32_t precision, int32_t group, int3
  * takes effect where the plan fits that build: site matrices of at most 64
  * rows with FP32 factorisations, 32 with FP64 ones, LDS within half a CU),
  * 0 = automatic; wg_per_cu (<= 4) then caps that build's work-groups per CU.
+ * With 256 threads, wg_per_cu = 1 or 2 keeps two groups per CU, 3, 4 or 0
+ * lets plans of at most 128 columns whose LDS fits a third of a CU run three
+ * (the default for them); a call whose segments of one precision include a
+ * plan on two groups per CU runs all of them in that one launch.
  * All zeros restore the default.  Returns TN_OK or TN_EINVAL. */
 int tn_set_tuning_ex(int32_t d, int32_t chi, int32_t precision, int32_t group, int32_t wg_per_cu, int32_t threads);
 

@@ -17,7 +17,7 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, f) for f in ("tnmld.hip", "tnmld_small.hip", "kacward.hip", "plan.cpp", "kw_plan.cpp")]
+    srcs = [os.path.join(CSRC, f) for f in ("tnmld.hip", "tnmld_small.hip", "tnmld_small3.hip", "kacward.hip", "plan.cpp", "kw_plan.cpp")]
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC] + FLAGS + ["-o", tmp] + srcs
     if verbose:

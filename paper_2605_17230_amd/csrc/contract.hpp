@@ -478,7 +478,7 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
           if (nn <= 128)
             lq_form_q_staged<Fac, Real, 8>((const glb_t<Fac>*)X, mJ, nn, nn, (const lds_t<Fac>*)tau,
                                            (lds_t<Fac>*)buf, cap, (glb_t<Real>*)g, nn);
-          else
+          else if constexpr (kMaxNpl >= 16)
             lq_form_q_staged<Fac, Real, 16>((const glb_t<Fac>*)X, mJ, nn, nn, (const lds_t<Fac>*)tau,
                                             (lds_t<Fac>*)buf, cap, (glb_t<Real>*)g, nn);
           staged = true;

@@ -464,14 +464,20 @@ __device__ __attribute__((noinline)) void lq_form_q(Real* X, int m, int n, int l
 // lq_rpg: rows per lane group: 2 with 512 threads; with 256 threads 4 for FP32
 // factorisations (64-row matrices in registers, as in the 512-thread build)
 // and 2 for FP64 ones (four rows of doubles would halve the waves per SIMD).
-constexpr int LQR_NPL = 16;
+// Widest register row a build compiles (columns per lane; 8 or 16): a build for
+// small plans leaves out the 16-column code, whose register use would cap its
+// occupancy.  Wider matrices take the LDS-resident factorisation there.
+#ifndef TNMLD_MAX_NPL
+#define TNMLD_MAX_NPL 16
+#endif
+constexpr int kMaxNpl = TNMLD_MAX_NPL;
 template <typename Real>
 constexpr int lq_rpg() {
   return NT >= 512 ? 2 : (sizeof(Real) == 4 ? 4 : 2);
 }
 template <typename Real>
 __device__ inline bool lq_regs_fit(int m, int n) {
-  return m <= lq_rpg<Real>() * (NT / 16) && n <= LQR_NPL * 16;
+  return m <= lq_rpg<Real>() * (NT / 16) && n <= kMaxNpl * 16;
 }
 // Row held in slot j by lane group g in the explicit-Q builder: slots pair a
 // row with its mirror (g and 2 NG - 1 - g, then 2 NG + g and 4 NG - 1 - g), so
@@ -728,7 +734,7 @@ __device__ inline __attribute__((always_inline)) void lq_factor_any(Real* X, int
     auto rl = (lds_t<double>*)red;
     auto vl = (lds_t<Real>*)vb;
     if (n <= 128) lq_factor_regs<Real, 8, XT>((XT*)X, m, n, ld, tl, dl, rl, vl);
-    else lq_factor_regs<Real, 16, XT>((XT*)X, m, n, ld, tl, dl, rl, vl);
+    else if constexpr (kMaxNpl >= 16) lq_factor_regs<Real, 16, XT>((XT*)X, m, n, ld, tl, dl, rl, vl);
   } else {
     lq_factor<Real>(X, m, n, ld, tau, diag, red);
   }
@@ -741,9 +747,11 @@ __device__ inline __attribute__((always_inline)) void lq_form_q_any(Real* X, int
     auto xl = (lds_t<Real>*)X;
     auto tl = (const lds_t<Real>*)tau;
     if (n == 128) lq_form_q_regs<Real, 8, true>(xl, m, n, ld, tl);
-    else if (n == 256) lq_form_q_regs<Real, 16, true>(xl, m, n, ld, tl);
     else if (n < 128) lq_form_q_regs<Real, 8, false>(xl, m, n, ld, tl);
-    else lq_form_q_regs<Real, 16, false>(xl, m, n, ld, tl);
+    else if constexpr (kMaxNpl >= 16) {
+      if (n == 256) lq_form_q_regs<Real, 16, true>(xl, m, n, ld, tl);
+      else lq_form_q_regs<Real, 16, false>(xl, m, n, ld, tl);
+    }
   } else {
     lq_form_q<Real>(X, m, n, ld, tau, v);
   }

@@ -47,6 +47,13 @@ int launch_bwd_small(int precision, const void* jt, char* scratch, int64_t strid
                      int flags, double* partials, int64_t pstride, int nwg, hipStream_t st);
 }  // namespace tnmld_small
 
+// The same kernel built for three 256-thread work-groups per CU (tnmld_small3.hip).
+namespace tnmld_small3 {
+int wgs_per_cu(int precision, int lds_bytes);
+int launch_fwd(int precision, const void* jt, unsigned long long* counter, char* scratch, int64_t stride,
+               int64_t snap_ofs, const void* lay, int lds_bytes, int nwg, hipStream_t st);
+}  // namespace tnmld_small3
+
 namespace tnmld {
 
 // Forward: persistent work-groups take syndromes (all four cosets each) from
@@ -394,11 +401,43 @@ bool small_plan(const PlanHeader& h, int precision) {
   return tnmld_small::small_wgs_per_cu(precision, lb, xg) >= 2;
 }
 
-constexpr int kMaxLaunches = 2 * (TN_BF16_F64 + 1);  // one per precision and size class
+// LDS of the three-groups-per-CU build within a third of a CU (plain layout,
+// else without the input site's LDS copy); -1 if neither fits.
+int small3_layout(const PlanHeader& h, int precision, bool* aj_global) {
+  const int limit = kLdsPerCU / 3 - 256;
+  for (int v = 0; v < 2; ++v) {
+    const int lb = lds_layout(h, real_bytes(precision), fac_bytes(precision), v == 1).bytes;
+    if (lb <= limit) {
+      *aj_global = v == 1;
+      return lb;
+    }
+  }
+  return -1;
+}
+
+// Plans whose factorisations all run in registers with at most 8 columns per
+// lane (site matrices of at most 128 columns in both sweeps) and whose LDS fits
+// a third of a CU run on the three-groups-per-CU build.
+bool small3_plan(const PlanHeader& h, int precision) {
+  const int rpg = fac_bytes(precision) == 4 ? 4 : 2;
+  if (h.max_m > rpg * (kSmallNT / 16) || h.max_kr > rpg * (kSmallNT / 16) || h.max_n > 128 ||
+      h.max_rows > 128 || h.max_bond > kSmallNT)
+    return false;
+  bool aj = false;
+  const int lb = small3_layout(h, precision, &aj);
+  if (lb < 0) return false;
+  return tnmld_small3::wgs_per_cu(precision, lb) >= 3;
+}
+
+// launch classes: the 512-thread build, the 256-thread build at two
+// work-groups per CU, and at three
+enum { BUILD_512 = 0, BUILD_256 = 1, BUILD_256X3 = 2, kNumBuilds = 3 };
+constexpr int kMaxLaunches = kNumBuilds * (TN_BF16_F64 + 1);  // one per precision and size class
 
 struct Launch {
   const Plan* host_plan[TN_MAX_SEGMENTS];  // plan of each job (host copy)
-  bool small;      // 256-thread build
+  int build;       // BUILD_*
+  bool small;      // a 256-thread build
   bool aj_global;  // small launch whose MPO step reads the input site from its region (LDS)
   bool x_global;   // small launch whose LQ matrix lives in the work-group's scratch (LDS)
   int precision;
@@ -448,29 +487,50 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
   for (int i = 0; i < nseg; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return segs[a].d > segs[b].d; });
   out->clear();
+  // the build each segment runs on: the 512-thread one when tuned so or when
+  // its plan needs it, else three 256-thread groups per CU where the plan
+  // fits (and no tuning says two), else two
+  std::vector<int> cls(nseg, BUILD_512);
+  std::vector<DevPlan*> plans(nseg, nullptr);
+  std::vector<Tune> tunes(nseg, Tune{0, 0, 0});
+  bool needs2[TN_BF16_F64 + 1] = {};
+  for (int i = 0; i < nseg; ++i) {
+    const tn_segment& s = segs[i];
+    if (s.count == 0) continue;
+    if (!precision_built(s.precision)) return fail(TN_EUNSUPPORTED, "precision not built");
+    const int rounds = s.rounds > 1 ? s.rounds : 1;
+    if ((rc = get_plan(s.d, s.chi, s.precision, lds_limit, &plans[i], upload, rounds))) return rc;
+    if (rounds == 1) {  // the tuned shapes are for one-round plans
+      std::lock_guard<std::mutex> lk(g_mu);
+      auto it = g_tune.find(std::make_tuple(s.d, s.chi, s.precision));
+      if (it != g_tune.end()) tunes[i] = it->second;
+    }
+    const Tune& tu = tunes[i];
+    const PlanHeader& h = plans[i]->plan.h;
+    if (!allow_small || tu.threads == NT) continue;
+    const bool two = tu.threads == kSmallNT && tu.wgs > 0 && tu.wgs < 3;
+    if (!two && small3_plan(h, s.precision)) cls[i] = BUILD_256X3;
+    else if (small_plan(h, s.precision)) cls[i] = BUILD_256;
+    if (cls[i] == BUILD_256) needs2[s.precision] = true;
+  }
+  // one persistent launch per precision and build: a precision whose call has
+  // plans on the two-group build runs its three-group plans there too
+  for (int i = 0; i < nseg; ++i)
+    if (cls[i] == BUILD_256X3 && needs2[segs[i].precision]) cls[i] = BUILD_256;
   for (int launch = 0; launch < kMaxLaunches; ++launch) {
-    const int prec = launch >> 1;
-    const bool small = (launch & 1) != 0;
-    if (small && !allow_small) continue;
+    const int prec = launch / kNumBuilds;
+    const int build = launch % kNumBuilds;
     Launch L{};
-    L.small = small;
+    L.build = build;
+    L.small = build != BUILD_512;
     L.precision = prec;
     int64_t items = 0;
     for (int oi : order) {
       const tn_segment& s = segs[oi];
-      if (s.precision != prec || s.count == 0) continue;
-      if (!precision_built(prec)) return fail(TN_EUNSUPPORTED, "precision not built");
-      DevPlan* dp = nullptr;
+      if (s.precision != prec || s.count == 0 || cls[oi] != build) continue;
+      DevPlan* dp = plans[oi];
+      const Tune& tu = tunes[oi];
       const int rounds = s.rounds > 1 ? s.rounds : 1;
-      if ((rc = get_plan(s.d, s.chi, prec, lds_limit, &dp, upload, rounds))) return rc;
-      Tune tu{0, 0, 0};
-      if (rounds == 1) {  // the tuned shapes are for one-round plans
-        std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_tune.find(std::make_tuple(s.d, s.chi, prec));
-        if (it != g_tune.end()) tu = it->second;
-      }
-      const bool want_small = allow_small && tu.threads != NT && small_plan(dp->plan.h, prec);
-      if (want_small != small) continue;
       L.host_plan[L.jt.n] = &dp->plan;
       JobDev& j = L.jt.j[L.jt.n++];
       j.plan = dp->dev;
@@ -488,12 +548,15 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
       L.scratch_elems = std::max<int64_t>(L.scratch_elems, dp->plan.h.scratch_elems);
       L.mps_elems = std::max<int64_t>(L.mps_elems, dp->plan.h.mps_elems);
       // a tuned work-groups-per-CU count applies to the build it was tuned on
+      const bool small = L.small;
       const int tw = (tu.threads == (small ? kSmallNT : NT) || (tu.threads == 0 && !small)) ? tu.wgs : 0;
       if (tw > 0) L.nwg = L.nwg ? std::min(L.nwg, tw) : tw;  // per-CU count for now
     }
     L.jt.nitems = items;
     L.aj_global = L.x_global = false;
-    if (small && small_layout(L.merged, prec, &L.aj_global, &L.x_global) < 0) {
+    if (build == BUILD_256X3) {
+      if (small3_layout(L.merged, prec, &L.aj_global) < 0) L.aj_global = true;  // merged: the compact layout
+    } else if (build == BUILD_256 && small_layout(L.merged, prec, &L.aj_global, &L.x_global) < 0) {
       // plans that fit one by one, merged: the most compact layout (the
       // work-groups per CU below follow from its LDS)
       L.aj_global = true;
@@ -507,7 +570,8 @@ int plan_launches(const tn_segment* segs, int32_t nseg, int lds_limit, std::vect
     const int lb = launch_layout(L).bytes;
     int w = wgs_for(lb, fwd_kernel_of(L.precision));
     if (L.small) {
-      const int ws = tnmld_small::small_wgs_per_cu(L.precision, lb, L.x_global);
+      const int ws = L.build == BUILD_256X3 ? tnmld_small3::wgs_per_cu(L.precision, lb)
+                                            : tnmld_small::small_wgs_per_cu(L.precision, lb, L.x_global);
       w = std::min(kLdsPerCU / (lb + 256), ws > 0 ? ws : 1);
       if (L.nwg > 0) w = std::min(w, L.nwg);  // tuned for the 256-thread build
     } else if (L.nwg > 0) {
@@ -551,9 +615,12 @@ int enqueue_forward(std::vector<Launch>& launches, char* header, char* regions, 
     if (L.small) {
       const LdsLayout lay = launch_layout(L);
       const int64_t stride = (int64_t)group_bytes(L);
-      if (tnmld_small::launch_fwd_small(L.precision, &L.jt, counter, scr, stride, L.scratch_elems, &lay, lay.bytes,
-                                        L.nwg, st) != 0)
-        return fail(TN_EDEVICE, "kernel launch failed");
+      const int r = L.build == BUILD_256X3
+                        ? tnmld_small3::launch_fwd(L.precision, &L.jt, counter, scr, stride, L.scratch_elems, &lay,
+                                                   lay.bytes, L.nwg, st)
+                        : tnmld_small::launch_fwd_small(L.precision, &L.jt, counter, scr, stride, L.scratch_elems,
+                                                        &lay, lay.bytes, L.nwg, st);
+      if (r != 0) return fail(TN_EDEVICE, "kernel launch failed");
       ++li;
       continue;
     }

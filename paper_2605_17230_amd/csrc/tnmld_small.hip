@@ -1,9 +1,11 @@
-// The forward kernel built for 256-thread work-groups, for plans whose site
-// matrices are small (at most 32 rows, chi <= 32): such items leave most of a
-// 512-thread group idle, and with 256 threads two work-groups share a CU and
-// hide each other's barrier and reduction latency.  Same device code as the
-// 512-thread build, compiled here in its own namespace; the host side of
-// tnmld.hip launches it through the two functions at the end.
+// The forward and backward kernels built for 256-thread work-groups, for plans
+// whose LQ rows fit this size's register rows (at most 64 rows with FP32
+// factorisations, 32 with FP64 ones; at most 256 columns): such items leave
+// much of a 512-thread group idle, and with 256 threads two work-groups share
+// a CU and hide each other's barrier and reduction latency.  Plans of at most
+// 128 columns run three groups per CU instead (tnmld_small3.hip).  Same device
+// code as the 512-thread build, compiled here in its own namespace; the host
+// side of tnmld.hip launches it through the functions at the end.
 #include <hip/hip_runtime.h>
 
 #include <map>

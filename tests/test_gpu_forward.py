@@ -279,6 +279,61 @@ def test_chi32_launch_shapes_vs_exact(dev, d, prec):
         check_classes(cls, ref, bar["logp"])
 
 
+@pytest.mark.parametrize("d,prec", [(5, "fp64"), (5, "fp32"), (5, "fp32plain"), (5, "bf16"), (7, "fp32"),
+                                    (9, "fp32"), (9, "fp32plain"), (9, "bf16")])
+def test_three_groups_per_cu_vs_exact(dev, d, prec):
+    """Plans whose site matrices have at most 128 columns run three 256-thread
+    work-groups per CU (the build without the 16-column register code).  It
+    runs the same arithmetic as two groups per CU, so the two agree bit for
+    bit.  Against the exact oracle: at d = 5, chi = 16 (no truncation) the
+    forms with FP64 factorisations meet the d = 5 bars, those with FP32 ones
+    the bars of the benchmark configuration (an all-FP32 run loses digits of
+    the less probable cosets in proportion to their posterior: about 1e-3 at
+    e^-7 on this sample, under either launch shape); at d = 7, 9 (truncated)
+    log P(s) within 1e-2 and classes, as for the p-sweep."""
+    import warnings
+    chi = 16 if d != 7 else 12
+    r = synth.depolarizing(d, 0.1) if d != 5 else synth.inhomogeneous(d, 0.005, 0.12, seed=5)
+    smp = synth.sample(d, r, 300, seed=5000 + d)
+    ref = oracle.transfer(d, r, smp["syndromes"], threads=8)
+    out = {}
+    for shape in [(2, 3, 256), (2, 2, 256)]:
+        tn.set_tuning(d, chi, prec, *shape)
+        try:
+            assert tuple(tn.api.launch_shape(d, chi, prec)) == shape
+            with warnings.catch_warnings():
+                warnings.simplefilter("ignore", tn.api.UnresolvedCosetsWarning)
+                out[shape[1]] = run(dev, d, chi, prec, smp["syndromes"], r)
+        finally:
+            tn.set_tuning(d, chi, prec)
+            tn.tune.load()
+    logz, logp, cls = out[3]
+    for a, b in zip(out[3], out[2]):
+        assert np.array_equal(a, b, equal_nan=True), "two and three groups per CU differ"
+    lp_ref, _ = oracle.decide(ref)
+    err_lp = float(np.max(np.abs(logp - lp_ref)))
+    if d == 5 and prec in ("fp64", "fp32"):
+        err = check_logz(logz, ref, prec)
+        check_classes(cls, ref, BOUND[prec])
+    elif d == 5:
+        bar = C3_BARS[prec]
+        fin, gfin = np.isfinite(ref), np.isfinite(logz)
+        assert not (gfin & ~fin).any()
+        post = np.where(fin, log_posterior(np.where(fin, ref, -np.inf)), -np.inf)
+        assert post[fin & ~gfin].max(initial=-np.inf) < UNRESOLVED_POST
+        both = fin & gfin
+        e = np.where(both, np.abs(np.where(both, logz, 0) - np.where(both, ref, 0)), 0.0)
+        err = float(e[post >= -10].max(initial=0))
+        assert err_lp < bar["logp"] and err < bar["post10"]
+        check_classes(cls, ref, bar["post10"])
+    else:
+        err = err_lp
+        assert err_lp < 1e-2
+        check_classes(cls, ref, 1e-2)
+    print("d=%d chi=%d %s, three groups/CU (bitwise equal to two): max |dlogP| %.3g, max |dlogZ| %.3g"
+          % (d, chi, prec, err_lp, err), flush=True)
+
+
 def test_deterministic_and_segment_independent(dev):
     segs = []
     ins = []

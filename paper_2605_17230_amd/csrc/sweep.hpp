@@ -106,6 +106,16 @@ __device__ inline double dpp_move(double v) {
   const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
+// Value of v on lane src of the wave (src uniform), to every lane.
+__device__ inline float lane_read(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ inline double lane_read(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
 #endif
 
 // Sum over aligned groups of G consecutive lanes (G a power of two <= 64),
@@ -522,14 +532,31 @@ __device__ __attribute__((noinline)) void lq_factor_regs(XT* X, int m, int n, in
       if (col == i) x0r = xr[c];
     }
     const double t2 = group_sum((tp[0] + tp[1]) + (tp[2] + tp[3]), 16);
+#ifdef TNMLD_EMU
     const double x0 = (double)group_sum(x0r, 16);  // one lane holds it: the sum is exact
+#else
+    // one lane holds it: read it there.  Only this group's lanes are active
+    // here (the caller's branch on the row it owns), so the first active
+    // lane gives the group's base lane in the wave.
+    const int src = __builtin_amdgcn_readfirstlane((int)threadIdx.x & (WAVE - 16)) + (i & 15);
+    const double x0 = (double)lane_read(x0r, src);
+#endif
     const double nrm = sqrt(t2 + x0 * x0);
     const bool live = t2 > 0.0 && nrm > TinyNorm<Real>::v;
     double beta = x0, td = 0.0, sd = 0.0;
     if (live) {
       beta = x0 >= 0.0 ? -nrm : nrm;
-      td = (beta - x0) / beta;
-      sd = 1.0 / (x0 - beta);
+      if constexpr (sizeof(Real) == 4) {
+        // one division: a = x0 - beta has |a| >= nrm, and beta a stays far
+        // inside the FP64 range for FP32 rows
+        const double a = x0 - beta;
+        const double rp = 1.0 / (beta * a);
+        td = -(a * a) * rp;  // (beta - x0) / beta
+        sd = beta * rp;      // 1 / (x0 - beta)
+      } else {
+        td = (beta - x0) / beta;
+        sd = 1.0 / (x0 - beta);
+      }
     }
     const Real t = Real(td), scale = Real(sd);
     lds_t<Real>* v = vb + (i & 1) * (16 * NPL);

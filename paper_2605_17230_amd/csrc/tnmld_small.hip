@@ -22,8 +22,10 @@
 
 namespace tnmld_small {
 
+// Two waves per SIMD (two groups per CU) is what this build is for; the
+// 16-column register code sits at the edge of that budget, so it is stated.
 template <typename Real, typename Fac, int GM, bool XG = false>
-__global__ __launch_bounds__(NT) void fwd_kernel_small(JobTable jt, unsigned long long* counter, char* scratch,
+__global__ __launch_bounds__(NT, 2) void fwd_kernel_small(JobTable jt, unsigned long long* counter, char* scratch,
                                                         int64_t scratch_stride, int64_t snap_ofs, LdsLayout lay) {
   extern __shared__ __align__(16) uint8_t smem[];
   Real* scr = reinterpret_cast<Real*>(scratch + (int64_t)blockIdx.x * scratch_stride);

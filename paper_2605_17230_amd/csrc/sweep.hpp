@@ -95,9 +95,12 @@ struct TinyNorm<float> {
 // traffic).  Controls: 0xB1 quad_perm [1,0,3,2], 0x4E quad_perm [2,3,0,1],
 // 0x141 row_half_mirror (lane i <- 7-i in each half-row), 0x140 row_mirror
 // (lane i <- 15-i).  Every lane of the row must be active.
+// The FP32 move names 0 (the sum's identity) as the value of a lane with no
+// source, so that the compiler folds it into the add that consumes it
+// (v_add_f32_dpp): one instruction per reduction step instead of two.
 template <int CTRL>
 __device__ inline float dpp_move(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 template <int CTRL>
 __device__ inline double dpp_move(double v) {

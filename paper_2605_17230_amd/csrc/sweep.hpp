@@ -561,12 +561,13 @@ __device__ __attribute__((noinline)) void lq_factor_regs(XT* X, int m, int n, in
         sd = 1.0 / (x0 - beta);
       }
     }
-    const Real t = Real(td), scale = Real(sd);
+    // with no reflection the tail is scaled by 1: exact, and no select per column
+    const Real t = Real(td), scale = live ? Real(sd) : Real(1);
     lds_t<Real>* v = vb + (i & 1) * (16 * NPL);
 #pragma unroll
     for (int c = 0; c < NPL; ++c) {
       const int col = lane + 16 * c;
-      if (live && col > i) xr[c] *= scale;
+      if (col > i) xr[c] *= scale;
       v[col] = col < i ? Real(0) : (col == i ? Real(1) : xr[c]);  // past column n, xr stays 0
     }
     if (lane == 0) {

@@ -121,6 +121,36 @@ __device__ inline double lane_read(double v, int src) {
 }
 #endif
 
+// Square root and reciprocal of a normal, finite FP64 value, for the
+// reflector scalars of FP32 rows (rounded to FP32 afterwards): the hardware
+// estimates refined by Newton steps (two for the reciprocal; for the root a
+// coupled root/half-inverse-root step and two residual corrections), about
+// an ulp of FP64, without the range scaling and special-value handling of
+// the IEEE forms.  The argument of sqrt_normal may be 0: the result is then
+// NaN, which the caller's tests treat as no reflection.
+__device__ inline double sqrt_normal(double s) {
+#ifdef TNMLD_EMU
+  return sqrt(s);
+#else
+  const double y = __builtin_amdgcn_rsq(s);
+  double g = s * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  g = fma(fma(-g, g, s), h, g);
+  return fma(fma(-g, g, s), h, g);
+#endif
+}
+__device__ inline double recip_normal(double p) {
+#ifdef TNMLD_EMU
+  return 1.0 / p;
+#else
+  double r = __builtin_amdgcn_rcp(p);
+  r = fma(r, fma(-p, r, 1.0), r);
+  return fma(r, fma(-p, r, 1.0), r);
+#endif
+}
+
 // Sum over aligned groups of G consecutive lanes (G a power of two <= 64),
 // returned to every lane of the group.  Partners add in commutative pairs, so
 // every lane of a group holds the bitwise-identical sum.  G <= 16 stays inside
@@ -544,7 +574,7 @@ __device__ __attribute__((noinline)) void lq_factor_regs(XT* X, int m, int n, in
     const int src = __builtin_amdgcn_readfirstlane((int)threadIdx.x & (WAVE - 16)) + (i & 15);
     const double x0 = (double)lane_read(x0r, src);
 #endif
-    const double nrm = sqrt(t2 + x0 * x0);
+    const double nrm = sizeof(Real) == 4 ? sqrt_normal(t2 + x0 * x0) : sqrt(t2 + x0 * x0);
     const bool live = t2 > 0.0 && nrm > TinyNorm<Real>::v;
     double beta = x0, td = 0.0, sd = 0.0;
     if (live) {
@@ -553,7 +583,7 @@ __device__ __attribute__((noinline)) void lq_factor_regs(XT* X, int m, int n, in
         // one division: a = x0 - beta has |a| >= nrm, and beta a stays far
         // inside the FP64 range for FP32 rows
         const double a = x0 - beta;
-        const double rp = 1.0 / (beta * a);
+        const double rp = recip_normal(beta * a);
         td = -(a * a) * rp;  // (beta - x0) / beta
         sd = beta * rp;      // 1 / (x0 - beta)
       } else {

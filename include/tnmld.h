@@ -268,6 +268,16 @@ int tn_set_tuning_ex(int32_t d, int32_t chi, int32_t precision, int32_t group, i
  * work-groups per CU, shape[2] threads per work-group.  shape: host int32[3]. */
 int tn_get_launch(int32_t d, int32_t chi, int32_t precision, int32_t* shape);
 
+/* HOST helper (needs a device): the persistent forward launches a
+ * tn_decode_batch call on these segments makes, in launch order (one per
+ * precision and build; the segments' pointers are not read).  For launch i
+ * < max_launches: out[4i] precision, out[4i+1] threads per work-group,
+ * out[4i+2] work-groups per CU, out[4i+3] segments it carries (empty
+ * segments carry none).  *count: the number of launches (may exceed
+ * max_launches).  out: host int32[4 * max_launches].  Returns TN_OK, or the
+ * error the call itself would return for these segments. */
+int tn_get_launches(const tn_segment* segs, int32_t nseg, int32_t* out, int32_t max_launches, int32_t* count);
+
 /* Status of the last tn_coset_loglik / tn_decode_batch /
  * tn_coset_loglik_backward call that used `workspace` (its input-value checks
  * and numerical health, see "Errors" above).  Synchronises `stream` (the

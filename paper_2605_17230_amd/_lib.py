@@ -78,6 +78,8 @@ def lib():
         L.tn_set_tuning_ex.argtypes = [I32, I32, I32, I32, I32, I32]
         L.tn_get_launch.restype = ctypes.c_int
         L.tn_get_launch.argtypes = [I32, I32, I32, ctypes.POINTER(I32)]
+        L.tn_get_launches.restype = ctypes.c_int
+        L.tn_get_launches.argtypes = [seg_p, I32, ctypes.POINTER(I32), I32, ctypes.POINTER(I32)]
         L.tn_decode_batch_noalloc.restype = ctypes.c_int
         L.tn_decode_batch_noalloc.argtypes = [seg_p, I32, D, P]
         L.tn_bitflip_workspace_size.restype = SZ

@@ -537,6 +537,20 @@ def launch_shape(d, chi, precision):
     return int(out[0]), int(out[1]), int(out[2])
 
 
+def launch_plan(segs):
+    """The persistent forward launches decode_segments(segs) makes, in order:
+    dicts of precision, threads, wg_per_cu and the number of segments each
+    carries."""
+    arr, _, _ = _prepare(segs, check=False)
+    cap = 3 * len(PRECISIONS)
+    out = (ctypes.c_int32 * (4 * cap))()
+    count = ctypes.c_int32(0)
+    check_rc(lib().tn_get_launches(arr, len(segs), out, cap, ctypes.byref(count)))
+    names = {v: k for k, v in PRECISIONS.items()}
+    return [dict(precision=names[out[4 * i]], threads=int(out[4 * i + 1]), wg_per_cu=int(out[4 * i + 2]),
+                 segments=int(out[4 * i + 3])) for i in range(min(count.value, cap))]
+
+
 def code_stabilizers(d):
     import numpy as np
     m = d * d - 1

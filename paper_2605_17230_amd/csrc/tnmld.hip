@@ -1115,6 +1115,26 @@ int tn_get_launch(int32_t d, int32_t chi, int32_t precision, int32_t* shape) {
   return TN_OK;
 }
 
+int tn_get_launches(const tn_segment* segs, int32_t nseg, int32_t* out, int32_t max_launches, int32_t* count) {
+  if (!out || !count || max_launches < 0) return fail(TN_EINVAL, "bad arguments");
+  std::vector<Launch> launches;
+  size_t need = 0;
+  int nwg = 0;
+  DevInfo di;
+  int rc = device_info(&di);
+  if (rc) return rc;
+  if ((rc = plan_launches(segs, nseg, std::min(di.lds_max, kLdsLimit), &launches, &need, &nwg))) return rc;
+  *count = (int32_t)launches.size();
+  for (size_t i = 0; i < launches.size() && i < (size_t)max_launches; ++i) {
+    const Launch& L = launches[i];
+    out[4 * i] = L.precision;
+    out[4 * i + 1] = L.small ? kSmallNT : NT;
+    out[4 * i + 2] = L.nwg / std::max(1, di.cus);
+    out[4 * i + 3] = L.jt.n;
+  }
+  return TN_OK;
+}
+
 int tn_workspace_status(const void* workspace, size_t ws_bytes, void* stream, int64_t* unresolved_cosets) {
   if (!workspace) {  // the allocation-free entry point's fixed array on the current device
     char* base = nullptr;

@@ -141,3 +141,28 @@ def test_graph_capture_replay():
             assert torch.equal(a.logp, b.logp)
             assert torch.equal(a.cls, b.cls)
     del eager
+
+
+def test_launch_plan_one_launch_per_precision_and_build():
+    """The mixed batch stays one persistent launch per form: d = 5..9 alone
+    would run three 256-thread groups per CU and d = 11..15 need two, so the
+    whole C4 batch runs on two.  The p-sweep (d = 9 only) runs on three; a
+    call with two forms makes one launch for each."""
+    tn = _tn()
+    c4 = synth.config_inputs("C4", scale=1 / 1024)
+    plan = tn.api.launch_plan(_inputs(c4, "bf16"))
+    print("C4 bf16:", plan, flush=True)
+    assert plan == [dict(precision="bf16", threads=256, wg_per_cu=2, segments=len(c4))]
+    small = [s for s in c4 if s["d"] <= 9]
+    plan = tn.api.launch_plan(_inputs(small, "bf16"))
+    print("C4 d <= 9, bf16:", plan, flush=True)
+    assert plan == [dict(precision="bf16", threads=256, wg_per_cu=3, segments=len(small))]
+    c2 = synth.config_inputs("C2", scale=1 / 4096)
+    plan = tn.api.launch_plan(_inputs(c2, "fp32plain"))
+    print("C2 fp32plain:", plan, flush=True)
+    assert plan == [dict(precision="fp32plain", threads=256, wg_per_cu=3, segments=len(c2))]
+    mixed = _inputs(small, "bf16") + _inputs(small, "fp32plain")
+    plan = tn.api.launch_plan(mixed)
+    print("two forms:", plan, flush=True)
+    assert len(plan) == 2 and {p["precision"] for p in plan} == {"bf16", "fp32plain"}
+    assert all(p["wg_per_cu"] == 3 and p["segments"] == len(small) for p in plan)

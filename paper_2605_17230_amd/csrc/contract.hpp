@@ -163,14 +163,23 @@ __device__ inline void report_dead(int dead, const ItemCheck& ck, const JobDev& 
 // Real: type of the MPS in HBM, of the MPO values and of the GEMM operands;
 // Fac: type of the LQ / SVD factorisations (LDS);
 // GM: how the two contraction GEMMs run: GEMM_VALU (Real arithmetic),
-// GEMM_BF16 (bf16 MFMA, FP32 accumulation) or GEMM_BF16X3 (split bf16).
-enum { GEMM_VALU = 0, GEMM_BF16 = 1, GEMM_BF16X3 = 2 };
+// GEMM_BF16 (bf16 MFMA, FP32 accumulation), GEMM_BF16X3 (split bf16) or
+// GEMM_F32 (FP32 MFMA: FP32 products, FP32 accumulation).
+enum { GEMM_VALU = 0, GEMM_BF16 = 1, GEMM_BF16X3 = 2, GEMM_F32 = 3 };
 
 template <int GM, typename Real, typename AL, typename BL, typename ST>
 __device__ inline void contract_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb, AL, BL,
                                      ST store) {
   if constexpr (GM == GEMM_VALU) {
     gemm_lds<Real>(M, N, K, A, lda, B, ldb, store);
+  } else if constexpr (GM == GEMM_F32) {
+#ifndef TNMLD_EMU
+    gemm_mfma_f32(
+        1, M, N, K, [&](int, int i, int k) { return (float)A[i * lda + k]; },
+        [&](int, int k, int j) { return (float)B[k * ldb + j]; }, [&](int, int i, int j, float v) { store(i, j, Real(v)); });
+#else
+    gemm_lds<Real>(M, N, K, A, lda, B, ldb, store);
+#endif
   } else {
 #ifndef TNMLD_EMU
     gemm_mfma_bf16<GM == GEMM_BF16X3>(
@@ -311,7 +320,7 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
   // the split form, split into hi/lo) once when they are written (T row-major,
   // L transposed; rows padded to 8)
 #ifndef TNMLD_EMU
-  constexpr bool PL = GM != GEMM_VALU && sizeof(Real) == 4;
+  constexpr bool PL = (GM == GEMM_BF16 || GM == GEMM_BF16X3) && sizeof(Real) == 4;
 #else
   constexpr bool PL = false;
 #endif
@@ -572,12 +581,19 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
         __syncthreads();
         // A[(l,so)][r] = sum_c Qf[c][(l,so)] W[c][perm r];  C[r][c'] = (Lf W)[c'][perm r]
 #ifndef TNMLD_EMU
-        if constexpr (GM != GEMM_VALU) {
+        if constexpr (GM == GEMM_BF16 || GM == GEMM_BF16X3) {
           // a GEMM (R x k2) . (k2 x Dn): on the bf16 matrix cores like the other contractions of this form
           gemm_mfma_bf16<GM == GEMM_BF16X3>(
               R, Dn, k2, [&](int lso, int c) { return (float)Mm[c * ldm + lso]; },
               [&](int c, int r) { return (float)Vv[perm[r] * ldl + c]; },
               [&](int lso, int r, float v) { g[lso * Dn + r] = Real(v); });
+        } else if constexpr (GM == GEMM_F32 && sizeof(Fac) == 4) {
+          // FP32 factorisations: the FP32 matrix cores (with FP64 ones this
+          // product belongs to the FP64 truncation and stays below)
+          gemm_mfma_f32(
+              1, R, Dn, k2, [&](int, int lso, int c) { return (float)Mm[c * ldm + lso]; },
+              [&](int, int c, int r) { return (float)Vv[perm[r] * ldl + c]; },
+              [&](int, int lso, int r, float v) { g[lso * Dn + r] = Real(v); });
         } else
 #endif
         {

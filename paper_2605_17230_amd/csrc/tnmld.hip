@@ -239,17 +239,17 @@ int ensure_lds_attr(const void* kern, int bytes) {
 
 const void* fwd_kernel_of(int precision) {
   if (precision == TN_FP64) return reinterpret_cast<const void*>(fwd_kernel<double, double, GEMM_VALU>);
-  if (precision == TN_FP32) return reinterpret_cast<const void*>(fwd_kernel<float, double, GEMM_VALU>);
+  if (precision == TN_FP32) return reinterpret_cast<const void*>(fwd_kernel<float, double, GEMM_F32>);
   if (precision == TN_BF16) return reinterpret_cast<const void*>(fwd_kernel<float, float, BF16_GEMM_MODE>);
   if (precision == TN_BF16_F64) return reinterpret_cast<const void*>(fwd_kernel<float, double, GEMM_BF16>);
-  return reinterpret_cast<const void*>(fwd_kernel<float, float, GEMM_VALU>);
+  return reinterpret_cast<const void*>(fwd_kernel<float, float, GEMM_F32>);
 }
 // (no adjoint for TN_BF16_F64: the backward planner rejects it before asking)
 const void* bwd_kernel_of(int precision) {
   if (precision == TN_FP64) return reinterpret_cast<const void*>(bwd_kernel<double, double, GEMM_VALU>);
-  if (precision == TN_FP32) return reinterpret_cast<const void*>(bwd_kernel<float, double, GEMM_VALU>);
+  if (precision == TN_FP32) return reinterpret_cast<const void*>(bwd_kernel<float, double, GEMM_F32>);
   if (precision == TN_BF16) return reinterpret_cast<const void*>(bwd_kernel<float, float, BF16_GEMM_MODE>);
-  return reinterpret_cast<const void*>(bwd_kernel<float, float, GEMM_VALU>);
+  return reinterpret_cast<const void*>(bwd_kernel<float, float, GEMM_F32>);
 }
 
 // Work-groups of `kern` that one CU holds at once with lds_bytes of dynamic
@@ -625,10 +625,10 @@ int enqueue_forward(std::vector<Launch>& launches, char* header, char* regions, 
       continue;
     }
     if (L.precision == TN_FP64) rc = launch_fwd<double, double, GEMM_VALU>(L, L.nwg, scr, counter, st);
-    else if (L.precision == TN_FP32) rc = launch_fwd<float, double, GEMM_VALU>(L, L.nwg, scr, counter, st);
+    else if (L.precision == TN_FP32) rc = launch_fwd<float, double, GEMM_F32>(L, L.nwg, scr, counter, st);
     else if (L.precision == TN_BF16) rc = launch_fwd<float, float, BF16_GEMM_MODE>(L, L.nwg, scr, counter, st);
     else if (L.precision == TN_BF16_F64) rc = launch_fwd<float, double, GEMM_BF16>(L, L.nwg, scr, counter, st);
-    else rc = launch_fwd<float, float, GEMM_VALU>(L, L.nwg, scr, counter, st);
+    else rc = launch_fwd<float, float, GEMM_F32>(L, L.nwg, scr, counter, st);
     if (rc) return rc;
     ++li;
   }

@@ -74,22 +74,22 @@ const void* kernel_of(int precision, bool xg = false) {
   if (xg) {
     if (precision == TN_BF16)
       return reinterpret_cast<const void*>(fwd_kernel_small<float, float, BF16_GEMM_MODE, true>);
-    if (precision == TN_FP32_PLAIN) return reinterpret_cast<const void*>(fwd_kernel_small<float, float, GEMM_VALU, true>);
+    if (precision == TN_FP32_PLAIN) return reinterpret_cast<const void*>(fwd_kernel_small<float, float, GEMM_F32, true>);
     return nullptr;
   }
   if (precision == TN_FP64) return reinterpret_cast<const void*>(fwd_kernel_small<double, double, GEMM_VALU>);
-  if (precision == TN_FP32) return reinterpret_cast<const void*>(fwd_kernel_small<float, double, GEMM_VALU>);
+  if (precision == TN_FP32) return reinterpret_cast<const void*>(fwd_kernel_small<float, double, GEMM_F32>);
   if (precision == TN_BF16) return reinterpret_cast<const void*>(fwd_kernel_small<float, float, BF16_GEMM_MODE>);
   if (precision == TN_BF16_F64) return reinterpret_cast<const void*>(fwd_kernel_small<float, double, GEMM_BF16>);
-  return reinterpret_cast<const void*>(fwd_kernel_small<float, float, GEMM_VALU>);
+  return reinterpret_cast<const void*>(fwd_kernel_small<float, float, GEMM_F32>);
 }
 
 const void* bwd_kernel_of(int precision) {
   if (precision == TN_BF16_F64) return nullptr;  // forward only
   if (precision == TN_FP64) return reinterpret_cast<const void*>(bwd_kernel_small<double, double, GEMM_VALU>);
-  if (precision == TN_FP32) return reinterpret_cast<const void*>(bwd_kernel_small<float, double, GEMM_VALU>);
+  if (precision == TN_FP32) return reinterpret_cast<const void*>(bwd_kernel_small<float, double, GEMM_F32>);
   if (precision == TN_BF16) return reinterpret_cast<const void*>(bwd_kernel_small<float, float, BF16_GEMM_MODE>);
-  return reinterpret_cast<const void*>(bwd_kernel_small<float, float, GEMM_VALU>);
+  return reinterpret_cast<const void*>(bwd_kernel_small<float, float, GEMM_F32>);
 }
 
 int raise_lds(const void* kern, int bytes) {

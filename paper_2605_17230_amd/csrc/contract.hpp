@@ -163,9 +163,10 @@ __device__ inline void report_dead(int dead, const ItemCheck& ck, const JobDev& 
 // Real: type of the MPS in HBM, of the MPO values and of the GEMM operands;
 // Fac: type of the LQ / SVD factorisations (LDS);
 // GM: how the two contraction GEMMs run: GEMM_VALU (Real arithmetic),
-// GEMM_BF16 (bf16 MFMA, FP32 accumulation), GEMM_BF16X3 (split bf16) or
-// GEMM_F32 (FP32 MFMA: FP32 products, FP32 accumulation).
-enum { GEMM_VALU = 0, GEMM_BF16 = 1, GEMM_BF16X3 = 2, GEMM_F32 = 3 };
+// GEMM_BF16 (bf16 MFMA, FP32 accumulation), GEMM_BF16X3 (split bf16),
+// GEMM_F32 (FP32 MFMA: FP32 products, FP32 accumulation) or GEMM_F64 (FP64
+// MFMA, for FP64 data).
+enum { GEMM_VALU = 0, GEMM_BF16 = 1, GEMM_BF16X3 = 2, GEMM_F32 = 3, GEMM_F64 = 4 };
 
 template <int GM, typename Real, typename AL, typename BL, typename ST>
 __device__ inline void contract_gemm(int M, int N, int K, const Real* A, int lda, const Real* B, int ldb, AL, BL,
@@ -177,6 +178,14 @@ __device__ inline void contract_gemm(int M, int N, int K, const Real* A, int lda
     gemm_mfma_f32(
         1, M, N, K, [&](int, int i, int k) { return (float)A[i * lda + k]; },
         [&](int, int k, int j) { return (float)B[k * ldb + j]; }, [&](int, int i, int j, float v) { store(i, j, Real(v)); });
+#else
+    gemm_lds<Real>(M, N, K, A, lda, B, ldb, store);
+#endif
+  } else if constexpr (GM == GEMM_F64) {
+#ifndef TNMLD_EMU
+    gemm_mfma_f64(
+        1, M, N, K, [&](int, int i, int k) { return (double)A[i * lda + k]; },
+        [&](int, int k, int j) { return (double)B[k * ldb + j]; }, [&](int, int i, int j, double v) { store(i, j, Real(v)); });
 #else
     gemm_lds<Real>(M, N, K, A, lda, B, ldb, store);
 #endif
@@ -587,6 +596,11 @@ __device__ bool row_step(const SiteStep* row, int nsite, const uint8_t* codes, c
               R, Dn, k2, [&](int lso, int c) { return (float)Mm[c * ldm + lso]; },
               [&](int c, int r) { return (float)Vv[perm[r] * ldl + c]; },
               [&](int lso, int r, float v) { g[lso * Dn + r] = Real(v); });
+        } else if constexpr (GM == GEMM_F64 && sizeof(Fac) == 8) {
+          gemm_mfma_f64(
+              1, R, Dn, k2, [&](int, int lso, int c) { return (double)Mm[c * ldm + lso]; },
+              [&](int, int c, int r) { return (double)Vv[perm[r] * ldl + c]; },
+              [&](int, int lso, int r, double v) { g[lso * Dn + r] = Real(v); });
         } else if constexpr (GM == GEMM_F32 && sizeof(Fac) == 4) {
           // FP32 factorisations: the FP32 matrix cores (with FP64 ones this
           // product belongs to the FP64 truncation and stays below)

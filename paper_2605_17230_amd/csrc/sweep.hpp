@@ -313,6 +313,34 @@ __device__ inline void gemm_mfma_f32(int nb, int M, int N, int K, ALoad aload, B
   }
 }
 
+// The same on the FP64 matrix cores (v_mfma_f64_16x16x4_f64: FP64 products
+// accumulated in FP64).  Operand lanes as above; output lane l value i is
+// row l/16 + 4i, column l%16 (the rows interleave, unlike the FP32 form).
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+template <typename ALoad, typename BLoad, typename Store>
+__device__ inline void gemm_mfma_f64(int nb, int M, int N, int K, ALoad aload, BLoad bload, Store store) {
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int tm = (M + 15) >> 4, tn = (N + 15) >> 4, per = tm * tn;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int t = wave; t < nb * per; t += NT / WAVE) {
+    const int bt = t / per, tt = t - bt * per;
+    const int i0 = (tt / tn) << 4, j0 = (tt % tn) << 4;
+    const int r = i0 + lr, c = j0 + lr;
+    f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int kk = k0 + lk;
+      const double a = (r < M && kk < K) ? aload(bt, r, kk) : 0.0;
+      const double b = (kk < K && c < N) ? bload(bt, kk, c) : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rr = i0 + lk + 4 * i;
+      if (rr < M && c < N) store(bt, rr, c, acc[i]);
+    }
+  }
+}
+
 // FP32 -> bf16 hi + lo (bits), the split of the three-product GEMMs.
 __device__ inline void split_bf16(float x, uint16_t& hi, uint16_t& lo) {
   const __bf16 h = (__bf16)x;

@@ -238,7 +238,7 @@ int ensure_lds_attr(const void* kern, int bytes) {
 }
 
 const void* fwd_kernel_of(int precision) {
-  if (precision == TN_FP64) return reinterpret_cast<const void*>(fwd_kernel<double, double, GEMM_VALU>);
+  if (precision == TN_FP64) return reinterpret_cast<const void*>(fwd_kernel<double, double, GEMM_F64>);
   if (precision == TN_FP32) return reinterpret_cast<const void*>(fwd_kernel<float, double, GEMM_F32>);
   if (precision == TN_BF16) return reinterpret_cast<const void*>(fwd_kernel<float, float, BF16_GEMM_MODE>);
   if (precision == TN_BF16_F64) return reinterpret_cast<const void*>(fwd_kernel<float, double, GEMM_BF16>);
@@ -624,7 +624,7 @@ int enqueue_forward(std::vector<Launch>& launches, char* header, char* regions, 
       ++li;
       continue;
     }
-    if (L.precision == TN_FP64) rc = launch_fwd<double, double, GEMM_VALU>(L, L.nwg, scr, counter, st);
+    if (L.precision == TN_FP64) rc = launch_fwd<double, double, GEMM_F64>(L, L.nwg, scr, counter, st);
     else if (L.precision == TN_FP32) rc = launch_fwd<float, double, GEMM_F32>(L, L.nwg, scr, counter, st);
     else if (L.precision == TN_BF16) rc = launch_fwd<float, float, BF16_GEMM_MODE>(L, L.nwg, scr, counter, st);
     else if (L.precision == TN_BF16_F64) rc = launch_fwd<float, double, GEMM_BF16>(L, L.nwg, scr, counter, st);

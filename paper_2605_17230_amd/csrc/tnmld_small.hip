@@ -77,7 +77,7 @@ const void* kernel_of(int precision, bool xg = false) {
     if (precision == TN_FP32_PLAIN) return reinterpret_cast<const void*>(fwd_kernel_small<float, float, GEMM_F32, true>);
     return nullptr;
   }
-  if (precision == TN_FP64) return reinterpret_cast<const void*>(fwd_kernel_small<double, double, GEMM_VALU>);
+  if (precision == TN_FP64) return reinterpret_cast<const void*>(fwd_kernel_small<double, double, GEMM_F64>);
   if (precision == TN_FP32) return reinterpret_cast<const void*>(fwd_kernel_small<float, double, GEMM_F32>);
   if (precision == TN_BF16) return reinterpret_cast<const void*>(fwd_kernel_small<float, float, BF16_GEMM_MODE>);
   if (precision == TN_BF16_F64) return reinterpret_cast<const void*>(fwd_kernel_small<float, double, GEMM_BF16>);

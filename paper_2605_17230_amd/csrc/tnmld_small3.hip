@@ -49,7 +49,7 @@ __global__ void zero_one3(unsigned long long* c) {
 
 namespace {
 const void* kernel_of(int precision) {
-  if (precision == TN_FP64) return reinterpret_cast<const void*>(fwd_kernel_small3<double, double, GEMM_VALU>);
+  if (precision == TN_FP64) return reinterpret_cast<const void*>(fwd_kernel_small3<double, double, GEMM_F64>);
   if (precision == TN_FP32) return reinterpret_cast<const void*>(fwd_kernel_small3<float, double, GEMM_F32>);
   if (precision == TN_BF16) return reinterpret_cast<const void*>(fwd_kernel_small3<float, float, BF16_GEMM_MODE>);
   if (precision == TN_BF16_F64) return reinterpret_cast<const void*>(fwd_kernel_small3<float, double, GEMM_BF16>);
